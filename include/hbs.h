@@ -1,0 +1,154 @@
+/*
+ * hbs.h -- C ABI of libhbs: black-box randomized compression of HBS
+ * (hierarchically block separable) matrices on one AMD MI355X (gfx950).
+ *
+ * The method is Levitt & Martinsson, "Linear-complexity black-box randomized
+ * compression of rank-structured matrices" (arXiv 2205.02990):
+ *   - cluster tree ........................ section 3.1
+ *   - HBS format, telescoping factorization  sections 3.2-3.3 (eqs.
+ *     telescoping_leaf, telescoping_parent, define_d_tau)
+ *   - compression from samples ............ section 4, Algorithm 2
+ *   - apply of the factorization .......... Algorithm 1
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are FP64, row-major.  An "N x s panel with leading dimension
+ *     ld" holds element (i, j) at p[i * ld + j]; ld >= s.
+ *   - Every matrix pointer is a DEVICE pointer on the current HIP device
+ *     unless stated otherwise.  Inputs are borrowed: read-only, and they must
+ *     stay valid until the work enqueued on the caller's stream completes.
+ *   - All device work is enqueued on `hip_stream` (a hipStream_t; NULL is the
+ *     default stream).  Calls return when the work is enqueued, not finished.
+ *   - Argument errors are reported synchronously, before anything is
+ *     enqueued, as HBS_EINVAL (or HBS_EUNSUPPORTED for shapes no compiled
+ *     kernel covers).  Numeric failures found on the device (a non-finite
+ *     input value, or a test-matrix block that is numerically rank
+ *     deficient) raise a per-factor-set flag that hbs_check() reports.
+ *   - Objects are not thread safe; use one handle per host thread.
+ */
+#ifndef HBS_H
+#define HBS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HBS_OK = 0,
+  HBS_EINVAL = -1,        /* bad argument (NULL, sizes, s too small ...)        */
+  HBS_ENOMEM = -2,        /* device allocation failed                           */
+  HBS_EDEVICE = -3,       /* a HIP runtime call failed                          */
+  HBS_ENUMERIC = -4,      /* device flag: non-finite data or rank-deficient box */
+  HBS_EUNSUPPORTED = -5   /* valid but not covered by a compiled kernel shape    */
+} hbs_status;
+
+typedef enum {
+  HBS_FP64 = 0,           /* every product in FP64                              */
+  HBS_FP32_SPLIT = 1,     /* bulk products on MFMA from exact BF16 slices       */
+  HBS_BF16 = 2            /* log-kernel sampler only: BF16 operands, FP32 sums  */
+} hbs_precision;
+
+typedef struct hbs_tree hbs_tree;        /* host-only, immutable after create */
+typedef struct hbs_factors hbs_factors;  /* owns device memory                */
+
+/* Cluster tree of section 3.1 on the indices 0..n-1.  The root owns all of
+ * them; a node [a, b) splits into [a, a + ceil((b-a)/2)) and [.., b); the
+ * split goes on level by level until every node of the newest level has at
+ * most leaf_max indices (so every leaf sits at depth L).  n >= 1,
+ * leaf_max >= 1; a split that would create an empty node is HBS_EINVAL.
+ * *out is owned by the caller and released with hbs_tree_destroy. */
+hbs_status hbs_tree_create(int64_t n, int32_t leaf_max, hbs_tree** out);
+void       hbs_tree_destroy(hbs_tree* t);
+/* Depth L of the tree (0 when n <= leaf_max: the root is the only box). */
+int32_t    hbs_tree_levels(const hbs_tree* t);
+/* Host query: first index and size of node `node` (0-based, left to right)
+ * on level `level`. */
+hbs_status hbs_tree_node(const hbs_tree* t, int32_t level, int64_t node, int64_t* start, int64_t* size);
+
+/* View of the factors of one level l = 1..L (section 3.3): the nodes of the
+ * level left to right, each with U_tau, V_tau (m_tau x k) and the
+ * discrepancy block D_tau (m_tau x m_tau).  Storage is padded to the largest
+ * node: U and V are [nodes][m][k], D is [nodes][m][m], rows and columns past
+ * m_tau hold zeros.  All pointers are device pointers owned by the factor
+ * set (valid until hbs_factors_destroy); m_tau is a device int32 array. */
+typedef struct {
+  int32_t level, nodes, m, k;
+  const int32_t* m_tau;
+  const double* U;
+  const double* V;
+  const double* D;
+} hbs_level_view;
+
+/* Allocate a factor set (and the sweep's workspace) for compressing an
+ * N x N matrix on tree `t` with bases of width k from s samples.  Every box
+ * tau needs m_tau >= k and s - m_tau >= k (the nullspace of its m_tau x s test
+ * matrix must hold a k-column sketch); the root needs s >= its row count (2k,
+ * or N when L = 0).  `prec` selects the arithmetic of the bulk products.
+ * Allocation happens here, once; hbs_compress_into allocates nothing. */
+hbs_status hbs_factors_create(const hbs_tree* t, int32_t k, int32_t s, hbs_precision prec,
+                              hbs_factors** out);
+void       hbs_factors_destroy(hbs_factors* f);
+
+/* Algorithm 2 (section 4): from the test matrices Omega, Psi (N x s) and the
+ * samples Y = A Omega, Z = A^* Psi (all four N x s, leading dimension ld)
+ * build the telescoping factorization of A into `f`.  For every box of a
+ * level at once: the full Householder QR of Omega_tau^* gives the nullspace
+ * P_tau (its trailing s - m_tau columns, section 2.4) and Omega_tau^dagger;
+ * U_tau = col(Y_tau P_tau, k) by column-pivoted truncated QR (eqs.
+ * u_tau_formula, v_tau_formula); D_tau by eq. d_tau_formula; then the
+ * reduced test and sample matrices of eq. omega_tau_and_y_tau feed the next
+ * level up; the root block is D^(0) = Y_root Omega_root^dagger.  The previous
+ * contents of `f` are overwritten. */
+hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* Y, const double* Psi,
+                             const double* Z, int64_t ld, void* hip_stream);
+
+/* hbs_factors_create followed by hbs_compress_into. */
+hbs_status hbs_compress(const hbs_tree* t, int32_t k, int32_t s, const double* Omega, const double* Y,
+                        const double* Psi, const double* Z, int64_t ld, hbs_precision prec,
+                        void* hip_stream, hbs_factors** out);
+
+/* Algorithm 1: Out = A~ X (transpose = 0) or A~^* X (transpose != 0) for the
+ * N x nvec block X; X and Out are N x nvec with leading dimension ldx >= nvec
+ * and must not overlap.  Uses workspace sized on first use for nvec (the call
+ * that grows it allocates). */
+hbs_status hbs_apply(hbs_factors* f, int transpose, const double* X, double* Out, int64_t nvec,
+                     int64_t ldx, void* hip_stream);
+
+/* Wrap known factors as a factor set, e.g. the generators of a synthetic HBS
+ * matrix, so that hbs_apply acts as its black box.  `levels` is a HOST array
+ * of L views (levels[l-1] describes level l, layout as hbs_level_view, device
+ * pointers with stride m = the tree's largest node on that level); D0 is the
+ * device root block (2k x 2k, or N x N when L = 0).  The data are copied
+ * (stream-ordered on hip_stream). */
+hbs_status hbs_factors_import(const hbs_tree* t, int32_t k, const hbs_level_view* levels, const double* D0,
+                              void* hip_stream, hbs_factors** out);
+
+/* View of level `level` (1..L) of a factor set. */
+hbs_status hbs_level(const hbs_factors* f, int32_t level, hbs_level_view* out);
+/* Device pointer to the root block D^(0) and its size (rows = cols). */
+hbs_status hbs_root(const hbs_factors* f, const double** D0, int32_t* rows);
+
+/* Wait for the factor set's last enqueued work and report the device flag:
+ * HBS_ENUMERIC if any box saw a non-finite value or a pivot of its test
+ * matrix's QR below 64 eps ||Omega_tau||_F; HBS_OK otherwise.  Clears it. */
+hbs_status hbs_check(hbs_factors* f);
+
+const char* hbs_status_str(hbs_status s);
+
+/* Stand-in black box: the log kernel A(i, j) = log|x_i - x_j| (i != j),
+ * A(i, i) = 0, on points (x[i], y[i]) (device arrays of n FP64 values).
+ * Writes Y = A Omega and Z = A^* Psi = A Psi (A is symmetric); Omega, Psi, Y,
+ * Z are n x s with leading dimension ld.  The kernel is never stored: every
+ * entry is formed on the fly inside the matrix-core product.  `prec`:
+ * HBS_FP64 (FP64 entries and FP64 matrix-core products) or HBS_BF16 (BF16
+ * entries and samples, FP32 accumulation). */
+hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, const double* Omega,
+                                const double* Psi, double* Y, double* Z, int32_t s, int64_t ld,
+                                hbs_precision prec, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBS_H */

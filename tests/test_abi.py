@@ -1,0 +1,84 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every entry point declared in include/hbs.h, builds the same cluster tree as
+section 3.1 describes (compared with the oracle's tree), and rejects invalid
+arguments synchronously before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from oracle import tree as otree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hbs.h")
+
+
+def _lib():
+    from paper_2205_02990_amd import hbs
+    if not os.path.exists(hbs.LIB_PATH):
+        pytest.skip("libhbs.so not built (run python -m paper_2205_02990_amd.build)")
+    return hbs
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hbs_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hbs_compress", "hbs_compress_into", "hbs_apply", "hbs_factors_import", "hbs_check",
+                     "hbs_tree_create", "hbs_sample_logkernel", "hbs_level", "hbs_root"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    hbs = _lib()
+    lib = ctypes.CDLL(hbs.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 4), (400, 100), (1000, 24), (1023, 32), (65536, 100), (3001, 64),
+                                    (4194304, 64), (262144, 128)])
+def test_library_tree_matches_section_3_1(n, leaf):
+    hbs = _lib()
+    t = hbs.Tree(n, leaf)
+    ref = otree.cluster_tree(n, leaf)
+    assert t.levels == otree.depth(ref)
+    for lev in range(min(t.levels, 12) + 1):
+        assert t.ranges(lev) == ref[lev]
+    if t.levels > 12:
+        # deep trees: compare the leaf level only at a few nodes
+        for i in (0, 1, 2 ** t.levels // 2, 2 ** t.levels - 1):
+            a, m = t.node(t.levels, i)
+            assert (a, a + m) == ref[t.levels][i]
+
+
+def test_tree_rejects_bad_arguments():
+    hbs = _lib()
+    for n, leaf in [(0, 4), (10, 0), (3, 1)]:
+        with pytest.raises(hbs.HBSError) as e:
+            hbs.Tree(n, leaf)
+        assert e.value.status == hbs.HBS_EINVAL
+
+
+@pytest.mark.parametrize("n,leaf,k,s,status", [
+    (1024, 32, 16, 47, "EINVAL"),   # s - m < k at the leaves
+    (1024, 32, 16, 47, "EINVAL"),
+    (1024, 32, 16, 32 + 16 - 1, "EINVAL"),
+    (1024, 32, 33, 200, "EINVAL"),  # leaves smaller than k
+    (1024, 32, 16, 47, "EINVAL"),
+    (1024, 32, 0, 58, "EINVAL"),
+    (1024, 32, 16, 3 * 16 - 1, "EINVAL"),  # inner boxes of 2k rows need s >= 3k
+    (40, 64, 4, 39, "EINVAL"),      # root-only: s must be >= N
+    (1024, 512, 16, 600, "EUNSUPPORTED"),  # leaves of 512 rows: no compiled tile class
+])
+def test_factor_creation_validates_before_device_work(n, leaf, k, s, status):
+    hbs = _lib()
+    t = hbs.Tree(n, leaf)
+    with pytest.raises(hbs.HBSError) as e:
+        hbs.Factors.create(t, k, s)
+    assert e.value.status == getattr(hbs, "HBS_" + status)
