@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Benchmark: HBS compression rows/s on one MI355X.
+
+One step = one full compression sweep (Algorithm 2: every level from the
+leaves to the root, all boxes of a level at once) of an N x N matrix from its
+samples {Omega, Y = A Omega, Psi, Z = A^* Psi}, which are resident in HBM when
+the timed region starts.  The samples come from the log-kernel stand-in
+black box (sampler timed separately, like the paper's compression time
+without the matvec).
+
+Output: one JSON line on stdout (rank 0).  Progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "HBS compression rows/s at fixed rel. apply error; mixed vs FP64 path, 1 GPU"
+PEAK_FP64_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # CUs x SIMDs x FP64 lanes x FMA x clock = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+# --------------------------------------------------------------------------
+# flop model (LAPACK operation counts of what one box computes)
+# --------------------------------------------------------------------------
+
+def side_flops(m, s, k, root=False):
+    """One side of one box: QR of the m x s test block (2 s m^2 - 2/3 m^3),
+    its m reflectors applied to the m x s sample block (4 m^2 s - 2 m^3), the
+    triangular solve for Y Omega^dagger (m^3), and - except at the root - the
+    truncated column-pivoted QR of the m x r sketch, r = s - m, stopped after k
+    steps (4 m r k - 2 (m + r) k^2 + 4/3 k^3) plus forming its m x k Q
+    (2 m k^2 - 2/3 k^3)."""
+    f = 2 * s * m * m - 2 * m ** 3 / 3 + 4 * m * m * s - 2 * m ** 3 + m ** 3
+    if not root:
+        r = s - m
+        f += 4 * m * r * k - 2 * (m + r) * k * k + 4 * k ** 3 / 3 + 2 * m * k * k - 2 * k ** 3 / 3
+    return f
+
+
+def combine_flops(m, k):
+    """D_tau: five m x m x k products."""
+    return 10 * m * m * k
+
+
+def parent_flops(m, s, k):
+    """V^* Omega, U^* Psi (2 m k s each) and U^*(Y - D Omega), V^*(Z - D^* Psi)
+    (2 m^2 s + 2 m k s each)."""
+    return 4 * m * k * s + 2 * (2 * m * m * s + 2 * m * k * s)
+
+
+def sweep_model(leaf_sizes, k, s):
+    """Per-step flop totals by kernel class, and the side kernel's launch count."""
+    L = int(round(math.log2(len(leaf_sizes))))
+    side = comb = par = 0.0
+    launches = 0
+    for lev in range(L, 0, -1):
+        ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
+        for m in ms:
+            side += 2 * side_flops(m, s, k)
+            comb += combine_flops(m, k)
+            par += parent_flops(m, s, k)
+        launches += 1
+    root = side_flops(2 * k if L > 0 else leaf_sizes[0], s, k, root=True)
+    return {"side": side, "combine": comb, "parent": par, "root": root, "side_launches": launches}
+
+
+def sweep_bytes(leaf_sizes, k, s):
+    """Algorithmic HBM bytes of the side kernel per step: each side of each box
+    reads its two m x s panels and writes W (m x m) and its basis (m x k)."""
+    L = int(round(math.log2(len(leaf_sizes))))
+    b = 0
+    for lev in range(L, 0, -1):
+        ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
+        for m in ms:
+            b += 2 * 8 * (2 * m * s + m * m + m * k)
+    return b
+
+
+# --------------------------------------------------------------------------
+# CPU baseline (oracle on a bounded sample)
+# --------------------------------------------------------------------------
+
+def cpu_baseline(wl, x, y, Om, Ps, sub_levels_below_root):
+    """Time the FP64 oracle on the subtree of the first node of level
+    `sub_levels_below_root`: all of that subtree's levels, on its own rows."""
+    import threadpoolctl
+    from oracle import hbs as ohbs
+    from oracle import logkernel as olog
+    from oracle import tree as otree
+    n = wl["n"]
+    full = otree.cluster_tree(n, wl["leaf_max"])
+    a, b = full[sub_levels_below_root][0]
+    rows = np.arange(a, b)
+    t0 = time.perf_counter()
+    G = np.hstack((Om, Ps))
+    YZ = olog.sample(x, y, G, rows)  # samples of the sample rows, formed by the oracle
+    Ys, Zs = YZ[:, :wl["s"]], YZ[:, wl["s"]:]
+    log(f"cpu baseline: oracle samples of rows [{a}, {b}) in {time.perf_counter() - t0:.1f} s")
+    sub = otree.cluster_tree(b - a, wl["leaf_max"])
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    t0 = time.perf_counter()
+    ohbs.compress(sub, wl["k"], Om[a:b], Ys, Ps[a:b], Zs)
+    dt = time.perf_counter() - t0
+    return {"value": (b - a) / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
+            "sample": (f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of level "
+                       f"{sub_levels_below_root} ({otree.depth(sub)} levels, all its boxes), "
+                       f"{dt:.1f} s; host os.cpu_count()={os.cpu_count()}")}
+
+
+# --------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="logkernel_ellipse_n65536_k50")
+    ap.add_argument("--path", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-subtree-level", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(multi-GPU sharding of the tree is a design note, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import inputs
+    from paper_2205_02990_amd import hbs
+
+    wl = dict(inputs.WORKLOADS[args.workload])
+    if wl["kind"] != "logkernel":
+        raise SystemExit("bench.py drives the log-kernel workloads")
+    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    hbs.load()
+
+    # ---- inputs (seeded, host) and samples (GPU black box) -----------------
+    rs = inputs.streams(wl["id"])
+    x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
+    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
+    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    Omd, Psd = torch.from_numpy(Om).to(dev), torch.from_numpy(Ps).to(dev)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd)  # warm
+    e0.record()
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd)
+    e1.record()
+    torch.cuda.synchronize()
+    sampler_ms = e0.elapsed_time(e1)
+    log(f"workload {args.workload}: N={n} k={k} leaf_max={leaf} s={s}; sampler {sampler_ms:.2f} ms")
+
+    tree = hbs.Tree(n, leaf)
+    leaf_sizes = tree.leaf_sizes()
+    f = hbs.Factors.create(tree, k, s, args.path)
+
+    # ---- warmup, then K timed sweeps ----------------------------------------
+    for _ in range(args.warmup):
+        f.compress_into(Omd, Yd, Psd, Zd)
+    torch.cuda.synchronize()
+    f.check()
+    f.profile(True)
+    f.profile_read()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        f.compress_into(Omd, Yd, Psd, Zd)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = e0.elapsed_time(e1)
+    prof = f.profile_read()
+    f.profile(False)
+    f.check()
+    ms_per_step = gpu_ms / args.steps
+    rows_per_s = n / (ms_per_step / 1e3)
+    log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms), "
+        f"{rows_per_s:.4g} rows/s; kernel ms/step: " +
+        ", ".join(f"{c} {v[0] / args.steps:.3f} ({v[1] // args.steps} launches)" for c, v in prof.items()))
+
+    # ---- accuracy of the result against the black box ------------------------
+    G = torch.from_numpy(inputs.probes(rs[inputs.STREAM_PROBES], n, 8)).to(dev)
+    AG, _ = hbs.sample_logkernel(xd, yd, G, G)
+    TG = f.apply(G)
+    rel_err = float(torch.linalg.norm(TG - AG) / torch.linalg.norm(AG))
+    in_sample = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
+    log(f"relative apply error vs the black box on 8 probes: {rel_err:.3e}; in-sample {in_sample:.3e}")
+
+    # ---- roofline of the dominant kernel (side kernel) -----------------------
+    model = sweep_model(leaf_sizes, k, s)
+    side_ms, side_launches = prof["side"][0] / args.steps, prof["side"][1] / args.steps
+    side_tflops = model["side"] / (side_ms / 1e3) / 1e12
+    per_launch = model["side"] / model["side_launches"]
+    traffic = None
+    tfile = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                         f"side_kernel_{args.workload}_traffic.json")
+    if os.path.exists(tfile):
+        with open(tfile) as fh:
+            tr = json.load(fh)
+        if tr.get("source_digest") == _side_digest():
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": round(side_tflops, 3), "peak": round(PEAK_FP64_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(side_tflops / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                "kernel": "side_kernel", "flops_per_launch": per_launch,
+                "avg_launch_ms": side_ms / side_launches,
+                "algorithmic_hbm_bytes_per_launch": sweep_bytes(leaf_sizes, k, s) / model["side_launches"]}
+    total_flops = model["side"] + model["combine"] + model["parent"] + model["root"]
+
+    out = {
+        "metric": METRIC, "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "N": n, "k": k, "leaf_max": leaf, "leaf": leaf_sizes[0], "s": s,
+                   "levels": tree.levels, "path": args.path},
+        "roofline": roofline,
+        "rel_apply_err": rel_err, "in_sample_err": in_sample,
+        "sampler_ms": sampler_ms, "rows_per_s_incl_sampler": n / ((ms_per_step + sampler_ms) / 1e3),
+        "sweep_tflops_model": total_flops / (ms_per_step / 1e3) / 1e12,
+        "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, x, y, Om, Ps, args.cpu_subtree_level)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} rows/s on {out['cpu_baseline']['cores']} threads")
+    print(json.dumps(out), flush=True)
+
+
+def _side_digest():
+    import hashlib
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2205_02990_amd", "csrc", "hbs_side.hip")
+    with open(p, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+if __name__ == "__main__":
+    main()

@@ -136,6 +136,19 @@ hbs_status hbs_check(hbs_factors* f);
 
 const char* hbs_status_str(hbs_status s);
 
+/* Kernel timing of the sweep (tracing, off by default).  With `enable` != 0,
+ * every later hbs_compress_into brackets each of its kernel launches with a
+ * pair of HIP events on the caller's stream.  Kernel classes:
+ *   0 side kernel (QR, nullspace sketch, solve, truncated QR: section 4.1-4.2)
+ *   1 discrepancy block D_tau (eq. d_tau_formula)
+ *   2 reduced samples for the parent level (eq. omega_tau_and_y_tau)
+ *   3 root block D^(0) */
+hbs_status hbs_profile(hbs_factors* f, int enable);
+/* Wait for the recorded work, then write the summed device time in ms and
+ * the launch count of each class (arrays of nclass <= 4 entries, host
+ * memory) accumulated since the previous read, and reset them. */
+hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass);
+
 /* Stand-in black box: the log kernel A(i, j) = log|x_i - x_j| (i != j),
  * A(i, i) = 0, on points (x[i], y[i]) (device arrays of n FP64 values).
  * Writes Y = A Omega and Z = A^* Psi = A Psi (A is symmetric); Omega, Psi, Y,

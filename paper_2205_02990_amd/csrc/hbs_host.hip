@@ -59,6 +59,31 @@ struct hbs_factors {
   std::vector<int64_t> hoff;  // row offset of level l's blocks in qhat/uhat
   hipStream_t last = nullptr;
   std::vector<void*> allocs;
+  // tracing: event pairs around launches (reused across sweeps)
+  bool prof = false;
+  struct Mark {
+    hipEvent_t a, b;
+    int cls;
+  };
+  std::vector<Mark> marks;
+  size_t nmarks = 0;
+
+  hipError_t mark_begin(int cls, hipStream_t st) {
+    if (!prof) return hipSuccess;
+    if (nmarks == marks.size()) {
+      Mark m{};
+      hipError_t e = hipEventCreate(&m.a);
+      if (e == hipSuccess) e = hipEventCreate(&m.b);
+      if (e != hipSuccess) return e;
+      marks.push_back(m);
+    }
+    marks[nmarks].cls = cls;
+    return hipEventRecord(marks[nmarks].a, st);
+  }
+  hipError_t mark_end(hipStream_t st) {
+    if (!prof) return hipSuccess;
+    return hipEventRecord(marks[nmarks++].b, st);
+  }
 
   hipError_t alloc(void** p, size_t bytes) {
     *p = nullptr;
@@ -68,6 +93,10 @@ struct hbs_factors {
     return e;
   }
   ~hbs_factors() {
+    for (Mark& m : marks) {
+      (void)hipEventDestroy(m.a);
+      (void)hipEventDestroy(m.b);
+    }
     for (void* p : allocs) (void)hipFree(p);
   }
 };
@@ -290,7 +319,9 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
     sa.X = f->X;
     sa.flag = f->flag;
     sa.root = 0;
+    HIP_TRY(f->mark_begin(0, st));
     HIP_TRY(hbs::launch_side(sa, st));
+    HIP_TRY(f->mark_end(st));
     hbs::CombineArgs ca{};
     ca.mtau = lv.mtau;
     ca.nodes = lv.nodes;
@@ -302,7 +333,9 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
     ca.X = f->X;
     ca.D = lv.D;
     ca.T = f->T;
+    HIP_TRY(f->mark_begin(1, st));
     HIP_TRY(hbs::launch_combine(ca, st));
+    HIP_TRY(f->mark_end(st));
     hbs::ParentArgs pa{};
     pa.Om = sa.Om;
     pa.Y = sa.Y;
@@ -323,7 +356,9 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
     pa.nY = up.bY;
     pa.nPs = up.bPs;
     pa.nZ = up.bZ;
+    HIP_TRY(f->mark_begin(2, st));
     HIP_TRY(hbs::launch_parent(pa, st));
+    HIP_TRY(f->mark_end(st));
   }
   // root: D^(0) = Y_root Omega_root^dagger
   Level& rt = f->lev[0];
@@ -346,7 +381,9 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
   sa.X = f->D0;
   sa.flag = f->flag;
   sa.root = 1;
+  HIP_TRY(f->mark_begin(3, st));
   HIP_TRY(hbs::launch_side(sa, st));
+  HIP_TRY(f->mark_end(st));
   return HBS_OK;
 }
 
@@ -510,6 +547,32 @@ hbs_status hbs_check(hbs_factors* f) {
   HIP_TRY(hipMemcpy(&flag, f->flag, sizeof(int32_t), hipMemcpyDeviceToHost));
   if (flag) HIP_TRY(hipMemset(f->flag, 0, sizeof(int32_t)));
   return flag ? HBS_ENUMERIC : HBS_OK;
+}
+
+hbs_status hbs_profile(hbs_factors* f, int enable) {
+  if (!f) return HBS_EINVAL;
+  f->prof = enable != 0;
+  return HBS_OK;
+}
+
+hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass) {
+  if (!f || !ms || !launches || nclass < 1 || nclass > 4) return HBS_EINVAL;
+  for (int c = 0; c < nclass; ++c) {
+    ms[c] = 0.0;
+    launches[c] = 0;
+  }
+  for (size_t i = 0; i < f->nmarks; ++i) {
+    const auto& m = f->marks[i];
+    HIP_TRY(hipEventSynchronize(m.b));
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, m.a, m.b));
+    if (m.cls < nclass) {
+      ms[m.cls] += t;
+      launches[m.cls] += 1;
+    }
+  }
+  f->nmarks = 0;
+  return HBS_OK;
 }
 
 hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, const double* Omega, const double* Psi,

@@ -61,6 +61,8 @@ def load():
         "hbs_check": (I32, [P]),
         "hbs_status_str": (ctypes.c_char_p, [I32]),
         "hbs_sample_logkernel": (I32, [I64, VP, VP, VP, VP, VP, VP, I32, I64, I32, VP]),
+        "hbs_profile": (I32, [P, ctypes.c_int]),
+        "hbs_profile_read": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -182,6 +184,18 @@ class Factors:
         if st == HBS_ENUMERIC:
             raise HBSError(st, "hbs_check")
         _check(st, "hbs_check")
+
+    def profile(self, enable: bool = True):
+        """Bracket every later sweep kernel with HIP events (see hbs_profile)."""
+        _check(load().hbs_profile(self._h, 1 if enable else 0), "hbs_profile")
+
+    def profile_read(self) -> dict:
+        """Summed device ms and launch counts per kernel class since the last read."""
+        ms = (ctypes.c_double * 4)()
+        n = (ctypes.c_int64 * 4)()
+        _check(load().hbs_profile_read(self._h, ms, n, 4), "hbs_profile_read")
+        names = ("side", "combine", "parent", "root")
+        return {names[i]: (ms[i], n[i]) for i in range(4)}
 
     def level(self, level: int, stream=None) -> dict:
         v = LevelView()
