@@ -1,6 +1,5 @@
 // Batched small products of the sweep and of the apply: one workgroup per box
-// (and per output block).  Operands stay in HBM/L2; each thread owns a strip
-// of output entries and runs the full inner product in FP64.
+// (and per output block), operands staged through LDS, FP64 register tiles.
 #include "hbs_internal.h"
 
 namespace hbs {
@@ -8,27 +7,98 @@ namespace {
 
 constexpr int kNT = 256;
 
-// C(i, j) = beta * C0(i, j) + alpha * sum_kk A(i, kk) B(kk, j) for i < M, j < N,
-// with A(i, kk) = A[i * sar + kk * sac] and B(kk, j) = B[kk * sbr + j * sbc].
-// C0 may alias C.  Called by every thread of the block.
-__device__ __forceinline__ void bgemm(int M, int N, int K, double alpha, const double* __restrict__ A,
-                                      int64_t sar, int64_t sac, const double* __restrict__ B, int64_t sbr,
-                                      int64_t sbc, double beta, const double* C0, int64_t ldc0, double* C,
-                                      int64_t ldc) {
-  for (int idx = threadIdx.x; idx < M * N; idx += blockDim.x) {
-    const int i = idx / N, j = idx % N;
-    const double* a = A + i * sar;
-    const double* b = B + j * sbc;
-    double acc0 = 0.0, acc1 = 0.0;
-    int kk = 0;
-    for (; kk + 1 < K; kk += 2) {
-      acc0 += a[kk * sac] * b[kk * sbr];
-      acc1 += a[(kk + 1) * sac] * b[(kk + 1) * sbr];
-    }
-    if (kk < K) acc0 += a[kk * sac] * b[kk * sbr];
-    const double v = alpha * (acc0 + acc1);
-    C[i * ldc + j] = (beta != 0.0) ? beta * C0[i * ldc0 + j] + v : v;
+// Block-level FP64 product through LDS, called by all kNT threads:
+//   C(i, j) = alpha * sum_kk A(i, kk) B(kk, j) + beta * C0(i, j),  i < M, j < N,
+// with A(i, kk) = A[i * sar + kk * sac] and B(kk, j) = B[kk * sbr + j * sbc]
+// (strides express transposes).  64 x 64 output tiles, 4 x 4 per thread,
+// K staged in chunks of 16; global loads are coalesced along whichever index
+// is contiguous.  C0 may alias C.  Ends with a barrier.
+constexpr int TM = 64, TN = 64, TK = 16;
+struct GemmSmem {
+  double As[TK][TM + 1];
+  double Bs[TK][TN + 1];
+};
+
+__device__ void tile_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int64_t sar,
+                          int64_t sac, const double* __restrict__ B, int64_t sbr, int64_t sbc, double beta,
+                          const double* C0, int64_t ldc0, double* C, int64_t ldc, GemmSmem& sm) {
+  constexpr int LA = (TM * TK) / kNT, LB = (TN * TK) / kNT;
+  const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
+  // per-thread element coordinates of the staged A and B chunks
+  int ai[LA], ak[LA], bj[LB], bk[LB];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int idx = tid + r * kNT;
+    ai[r] = (sac == 1) ? idx / TK : idx % TM;
+    ak[r] = (sac == 1) ? idx % TK : idx / TM;
   }
+#pragma unroll
+  for (int r = 0; r < LB; ++r) {
+    const int idx = tid + r * kNT;
+    bj[r] = (sbc == 1) ? idx % TN : idx / TK;
+    bk[r] = (sbc == 1) ? idx / TN : idx % TK;
+  }
+  for (int i0 = 0; i0 < M; i0 += TM) {
+    for (int j0 = 0; j0 < N; j0 += TN) {
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+      double pa[LA], pb[LB];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+          const int gi = i0 + ai[r], gk = k0 + ak[r];
+          const bool ok = gi < M && gk < K;
+          const double v = A[ok ? gi * sar + gk * sac : 0];
+          pa[r] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < LB; ++r) {
+          const int gj = j0 + bj[r], gk = k0 + bk[r];
+          const bool ok = gj < N && gk < K;
+          const double v = B[ok ? gk * sbr + gj * sbc : 0];
+          pb[r] = ok ? v : 0.0;
+        }
+      };
+      fetch(0);
+      for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) sm.As[ak[r]][ai[r]] = pa[r];
+#pragma unroll
+        for (int r = 0; r < LB; ++r) sm.Bs[bk[r]][bj[r]] = pb[r];
+        __syncthreads();
+        if (k0 + TK < K) fetch(k0 + TK);  // next chunk in flight during the products
+#pragma unroll 4
+        for (int kk = 0; kk < TK; ++kk) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int a = 0; a < 4; ++a) av[a] = sm.As[kk][ty + 16 * a];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) bv[b] = sm.Bs[kk][tx + 16 * b];
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int gi = i0 + ty + 16 * a;
+        if (gi >= M) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int gj = j0 + tx + 16 * b;
+          if (gj >= N) continue;
+          const double v = alpha * acc[a][b];
+          C[gi * ldc + gj] = (beta != 0.0) ? beta * C0[gi * ldc0 + gj] + v : v;
+        }
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // D_tau of eq. d_tau_formula, evaluated as
@@ -47,16 +117,14 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
   double* Xp = T1 + mm * k;                                  // m x m
   double* E = Xp + mm * mm;                                  // m x k
   double* T2 = E + mm * k;                                   // k x m
+  __shared__ GemmSmem sm;
   // T1 = V^* X
-  bgemm(k, m, m, 1.0, V, 1, k, X, mm, 1, 0.0, nullptr, 0, T1, m);
-  __syncthreads();
+  tile_gemm(k, m, m, 1.0, V, 1, k, X, mm, 1, 0.0, nullptr, 0, T1, m, sm);
   // X' = X - V T1
-  bgemm(m, m, k, -1.0, V, k, 1, T1, m, 1, 1.0, X, mm, Xp, m);
-  __syncthreads();
+  tile_gemm(m, m, k, -1.0, V, k, 1, T1, m, 1, 1.0, X, mm, Xp, m, sm);
   // E = X' U ; T2 = U^* W
-  bgemm(m, k, m, 1.0, Xp, m, 1, U, k, 1, 0.0, nullptr, 0, E, k);
-  bgemm(k, m, m, 1.0, U, 1, k, W, mm, 1, 0.0, nullptr, 0, T2, m);
-  __syncthreads();
+  tile_gemm(m, k, m, 1.0, Xp, m, 1, U, k, 1, 0.0, nullptr, 0, E, k, sm);
+  tile_gemm(k, m, m, 1.0, U, 1, k, W, mm, 1, 0.0, nullptr, 0, T2, m, sm);
   // T2 <- T2 - E^*
   for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {
     const int i = idx / m, j = idx % m;
@@ -64,7 +132,7 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
   }
   __syncthreads();
   // D = W - U T2
-  bgemm(m, m, k, -1.0, U, k, 1, T2, m, 1, 1.0, W, mm, D, mm);
+  tile_gemm(m, m, k, -1.0, U, k, 1, T2, m, 1, 1.0, W, mm, D, mm, sm);
   // zero padding of D (rows/cols m .. mm-1)
   for (int idx = threadIdx.x; idx < mm * mm; idx += blockDim.x) {
     const int i = idx / mm, j = idx % mm;
@@ -78,30 +146,32 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
 //   y = 2: U^* Psi_tau        y = 3: V^* (Z_tau - D_tau^* Psi_tau)
 // Child t writes rows [k t, k t + k) of the next level's panels (ld = s).
 __global__ void __launch_bounds__(kNT) parent_kernel(ParentArgs a) {
+  __shared__ GemmSmem sm;
   const int box = blockIdx.x, which = blockIdx.y;
+  const int c0 = blockIdx.z * TN;
   const int m = a.mtau[box], k = a.k, s = a.s, mm = a.mmax;
+  const int nc = (s - c0) < TN ? (s - c0) : TN;
   const int64_t ld = a.ld;
   const int64_t r0 = a.row0[box];
   const double* U = a.U + (int64_t)box * mm * k;
   const double* V = a.V + (int64_t)box * mm * k;
   const double* D = a.D + (int64_t)box * mm * mm;
   const double* Bas = (which == 0 || which == 3) ? V : U;
-  const double* Tst = ((which < 2) ? a.Om : a.Ps) + r0 * ld;
+  const double* Tst = ((which < 2) ? a.Om : a.Ps) + r0 * ld + c0;
   double* out = ((which == 0) ? a.nOm : (which == 1) ? a.nY : (which == 2) ? a.nPs : a.nZ) +
-                (int64_t)box * k * s;
+                (int64_t)box * k * s + c0;
   if (which == 0 || which == 2) {
-    bgemm(k, s, m, 1.0, Bas, 1, k, Tst, ld, 1, 0.0, nullptr, 0, out, s);
+    tile_gemm(k, nc, m, 1.0, Bas, 1, k, Tst, ld, 1, 0.0, nullptr, 0, out, s, sm);
     return;
   }
-  const double* Smp = ((which == 1) ? a.Y : a.Z) + r0 * ld;
-  double* R = a.R + ((int64_t)box * 2 + (which == 3)) * mm * s;
-  // R = Smp - D Tst  (or D^*)
+  const double* Smp = ((which == 1) ? a.Y : a.Z) + r0 * ld + c0;
+  double* R = a.R + ((int64_t)box * 2 + (which == 3)) * mm * s + c0;
+  // R = Smp - D Tst  (D^* for the Z side)
   if (which == 1)
-    bgemm(m, s, m, -1.0, D, mm, 1, Tst, ld, 1, 1.0, Smp, ld, R, s);
+    tile_gemm(m, nc, m, -1.0, D, mm, 1, Tst, ld, 1, 1.0, Smp, ld, R, s, sm);
   else
-    bgemm(m, s, m, -1.0, D, 1, mm, Tst, ld, 1, 1.0, Smp, ld, R, s);
-  __syncthreads();
-  bgemm(k, s, m, 1.0, Bas, 1, k, R, s, 1, 0.0, nullptr, 0, out, s);
+    tile_gemm(m, nc, m, -1.0, D, 1, mm, Tst, ld, 1, 1.0, Smp, ld, R, s, sm);
+  tile_gemm(k, nc, m, 1.0, Bas, 1, k, R, s, 1, 0.0, nullptr, 0, out, s, sm);
 }
 
 // Upward pass of Algorithm 1 on one level: qhat_tau = B_tau^* in_tau, where
@@ -112,7 +182,8 @@ __global__ void __launch_bounds__(kNT) apply_up_kernel(ApplyArgs a) {
   const double* Bas = a.B1 + (int64_t)box * a.mmax * k;
   const double* in = a.in + (a.leaf ? a.row0[box] : (int64_t)box * m) * a.ld_in;
   double* out = a.out + (int64_t)box * k * a.ld_out;
-  bgemm(k, (int)a.nvec, m, 1.0, Bas, 1, k, in, a.ld_in, 1, 0.0, nullptr, 0, out, a.ld_out);
+  __shared__ GemmSmem sm;
+  tile_gemm(k, (int)a.nvec, m, 1.0, Bas, 1, k, in, a.ld_in, 1, 0.0, nullptr, 0, out, a.ld_out, sm);
 }
 
 // Downward pass of Algorithm 1 on one level:
@@ -128,29 +199,27 @@ __global__ void __launch_bounds__(kNT) apply_down_kernel(ApplyArgs a) {
   const double* uh = a.in + (int64_t)box * k * a.ld_in;
   const double* qin = a.qin + rows * a.ld_q;
   double* out = a.out + rows * a.ld_out;
-  for (int idx = threadIdx.x; idx < m * nv; idx += blockDim.x) {
-    const int i = idx / nv, j = idx % nv;
-    double acc = 0.0;
-    for (int kk = 0; kk < k; ++kk) acc += Bas[i * k + kk] * uh[kk * a.ld_in + j];
-    if (a.transD)
-      for (int kk = 0; kk < m; ++kk) acc += D[kk * mm + i] * qin[kk * a.ld_q + j];
-    else
-      for (int kk = 0; kk < m; ++kk) acc += D[i * mm + kk] * qin[kk * a.ld_q + j];
-    out[i * a.ld_out + j] = acc;
-  }
+  __shared__ GemmSmem sm;
+  // out = B uhat, then out += D qin (or D^* qin)
+  tile_gemm(m, nv, k, 1.0, Bas, k, 1, uh, a.ld_in, 1, 0.0, nullptr, 0, out, a.ld_out, sm);
+  if (a.transD)
+    tile_gemm(m, nv, m, 1.0, D, 1, mm, qin, a.ld_q, 1, 1.0, out, a.ld_out, out, a.ld_out, sm);
+  else
+    tile_gemm(m, nv, m, 1.0, D, mm, 1, qin, a.ld_q, 1, 1.0, out, a.ld_out, out, a.ld_out, sm);
 }
 
 // Plain C = op(A) B for the root block (one workgroup per 64 rows).
 __global__ void __launch_bounds__(kNT) dense_small_kernel(const double* A, int64_t lda, int32_t transA,
                                                           const double* Bm, int64_t ldb, double* C, int64_t ldc,
                                                           int32_t M, int32_t N, int32_t K) {
+  __shared__ GemmSmem sm;
   const int r0 = blockIdx.x * 64;
   const int mrows = (M - r0) < 64 ? (M - r0) : 64;
   if (transA)
-    bgemm(mrows, N, K, 1.0, A + r0, 1, lda, Bm, ldb, 1, 0.0, nullptr, 0, C + (int64_t)r0 * ldc, ldc);
+    tile_gemm(mrows, N, K, 1.0, A + r0, 1, lda, Bm, ldb, 1, 0.0, nullptr, 0, C + (int64_t)r0 * ldc, ldc, sm);
   else
-    bgemm(mrows, N, K, 1.0, A + (int64_t)r0 * lda, lda, 1, Bm, ldb, 1, 0.0, nullptr, 0, C + (int64_t)r0 * ldc,
-          ldc);
+    tile_gemm(mrows, N, K, 1.0, A + (int64_t)r0 * lda, lda, 1, Bm, ldb, 1, 0.0, nullptr, 0, C + (int64_t)r0 * ldc,
+              ldc, sm);
 }
 
 }  // namespace
@@ -161,7 +230,7 @@ hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_parent(const ParentArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(parent_kernel, dim3(a.nodes, 4), dim3(kNT), 0, st, a);
+  hipLaunchKernelGGL(parent_kernel, dim3(a.nodes, 4, (a.s + TN - 1) / TN), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 

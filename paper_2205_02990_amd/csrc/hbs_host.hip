@@ -51,6 +51,7 @@ struct hbs_factors {
   double* X = nullptr;
   double* T = nullptr;
   double* R = nullptr;
+  double* Bt = nullptr;
   int32_t* flag = nullptr;
   // apply workspace
   double* qhat = nullptr;
@@ -107,7 +108,7 @@ hbs_status build_levels(hbs_factors* f, bool with_workspace) {
   const hbs_tree& t = f->tree;
   const int L = t.L, k = f->k, s = f->s;
   f->lev.assign(L + 1, Level{});
-  size_t wmax = 0, tmax = 0, rmax = 0;
+  size_t wmax = 0, tmax = 0, rmax = 0, bmax = 0;
   for (int l = 0; l <= L; ++l) {
     Level& lv = f->lev[l];
     lv.nodes = 1 << l;
@@ -142,6 +143,7 @@ hbs_status build_levels(hbs_factors* f, bool with_workspace) {
       wmax = std::max(wmax, (size_t)lv.nodes * lv.mmax * lv.mmax);
       tmax = std::max(tmax, (size_t)lv.nodes * ((size_t)lv.mmax * lv.mmax + 3 * (size_t)lv.mmax * k));
       rmax = std::max(rmax, (size_t)lv.nodes * 2 * lv.mmax * s);
+      bmax = std::max(bmax, (size_t)lv.nodes * 2 * s * lv.mmax);
     }
     if (with_workspace && l < L) {
       const size_t nb = (size_t)lv.nodes * 2 * k * s * sizeof(double);
@@ -161,6 +163,7 @@ hbs_status build_levels(hbs_factors* f, bool with_workspace) {
     if ((e = f->alloc((void**)&f->X, sizeof(double) * wmax)) != hipSuccess) return from_hip(e);
     if ((e = f->alloc((void**)&f->T, sizeof(double) * tmax)) != hipSuccess) return from_hip(e);
     if ((e = f->alloc((void**)&f->R, sizeof(double) * rmax)) != hipSuccess) return from_hip(e);
+    if ((e = f->alloc((void**)&f->Bt, sizeof(double) * bmax)) != hipSuccess) return from_hip(e);
   }
   f->hoff.assign(L + 2, 0);
   for (int l = 1; l <= L; ++l) f->hoff[l + 1] = f->hoff[l] + (int64_t)(1 << l) * k;
@@ -317,6 +320,7 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
     sa.V = lv.V;
     sa.W = f->W;
     sa.X = f->X;
+    sa.Bt = f->Bt;
     sa.flag = f->flag;
     sa.root = 0;
     HIP_TRY(f->mark_begin(0, st));
@@ -379,6 +383,7 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
   sa.V = nullptr;
   sa.W = f->D0;
   sa.X = f->D0;
+  sa.Bt = nullptr;
   sa.flag = f->flag;
   sa.root = 1;
   HIP_TRY(f->mark_begin(3, st));

@@ -24,6 +24,7 @@ struct SideArgs {
   double* V;
   double* W;  // [nodes][mmax][mmax] Y_tau Omega_tau^dagger (side 0) / Z Psi^dagger (side 1)
   double* X;
+  double* Bt;  // [nodes][2][s][mmax] transposed sketches (Y P)^*, (Z Q)^*
   int32_t* flag;
   int32_t root;  // 1: only W = Y Omega^dagger of the single box (written to W)
 };
