@@ -11,17 +11,20 @@ constexpr int kNT = 256;
 //   C(i, j) = alpha * sum_kk A(i, kk) B(kk, j) + beta * C0(i, j),  i < M, j < N,
 // with A(i, kk) = A[i * sar + kk * sac] and B(kk, j) = B[kk * sbr + j * sbc]
 // (strides express transposes).  64 x 64 output tiles, 4 x 4 per thread,
-// K staged in chunks of 16; global loads are coalesced along whichever index
+// K staged in chunks of TK (deeper chunks: fewer memory round trips on the
+// latency-bound levels near the root, more registers); global loads are coalesced along whichever index
 // is contiguous.  C0 may alias C.  Ends with a barrier.
-constexpr int TM = 64, TN = 64, TK = 16;
+constexpr int TM = 64, TN = 64;
+template <int TK>
 struct GemmSmem {
   double As[TK][TM + 1];
   double Bs[TK][TN + 1];
 };
 
+template <int TK>
 __device__ void tile_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int64_t sar,
                           int64_t sac, const double* __restrict__ B, int64_t sbr, int64_t sbc, double beta,
-                          const double* C0, int64_t ldc0, double* C, int64_t ldc, GemmSmem& sm) {
+                          const double* C0, int64_t ldc0, double* C, int64_t ldc, GemmSmem<TK>& sm) {
   constexpr int LA = (TM * TK) / kNT, LB = (TN * TK) / kNT;
   const int tid = threadIdx.x, ty = tid / 16, tx = tid % 16;
   // per-thread element coordinates of the staged A and B chunks
@@ -102,10 +105,11 @@ __device__ void tile_gemm(int M, int N, int K, double alpha, const double* __res
 }
 
 // D_tau of eq. d_tau_formula, evaluated as
-//   T1 = V^* X, X' = X - V T1 = (I - V V^*) X, E = X' U,
-//   T2 = U^* W, D = W - U (T2 - E^*) = (I - U U^*) W + U (X' U)^*
-//     = (I - U U^*) W + U U^* ((I - V V^*) X)^*.
+//   F = X U,  G = V^* F,  E = F - V G = (I - V V^*) X U,
+//   T = U^* W - E^*,  D = W - U T = (I - U U^*) W + U U^* ((I - V V^*) X)^*.
+template <int TK>
 __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
+  __shared__ GemmSmem<TK> sm;
   const int box = blockIdx.x;
   const int m = a.mtau[box], k = a.k, mm = a.mmax;
   const double* U = a.U + (int64_t)box * mm * k;
@@ -113,26 +117,20 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
   const double* W = a.W + (int64_t)box * mm * mm;
   const double* X = a.X + (int64_t)box * mm * mm;
   double* D = a.D + (int64_t)box * mm * mm;
-  double* T1 = a.T + (int64_t)box * (mm * mm + 3 * mm * k);  // k x m
-  double* Xp = T1 + mm * k;                                  // m x m
-  double* E = Xp + mm * mm;                                  // m x k
-  double* T2 = E + mm * k;                                   // k x m
-  __shared__ GemmSmem sm;
-  // T1 = V^* X
-  tile_gemm(k, m, m, 1.0, V, 1, k, X, mm, 1, 0.0, nullptr, 0, T1, m, sm);
-  // X' = X - V T1
-  tile_gemm(m, m, k, -1.0, V, k, 1, T1, m, 1, 1.0, X, mm, Xp, m, sm);
-  // E = X' U ; T2 = U^* W
-  tile_gemm(m, k, m, 1.0, Xp, m, 1, U, k, 1, 0.0, nullptr, 0, E, k, sm);
-  tile_gemm(k, m, m, 1.0, U, 1, k, W, mm, 1, 0.0, nullptr, 0, T2, m, sm);
-  // T2 <- T2 - E^*
+  double* F = a.T + (int64_t)box * (mm * mm + 3 * mm * k);  // m x k
+  double* Gm = F + mm * k;                                  // k x k
+  double* E = Gm + mm * k;                                  // m x k
+  double* T = E + mm * k;                                   // k x m
+  tile_gemm(m, k, m, 1.0, X, mm, 1, U, k, 1, 0.0, nullptr, 0, F, k, sm);       // F = X U
+  tile_gemm(k, k, m, 1.0, V, 1, k, F, k, 1, 0.0, nullptr, 0, Gm, k, sm);      // G = V^* F
+  tile_gemm(m, k, k, -1.0, V, k, 1, Gm, k, 1, 1.0, F, k, E, k, sm);           // E = F - V G
+  tile_gemm(k, m, m, 1.0, U, 1, k, W, mm, 1, 0.0, nullptr, 0, T, m, sm);      // T = U^* W
   for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {
     const int i = idx / m, j = idx % m;
-    T2[i * m + j] -= E[j * k + i];
+    T[i * m + j] -= E[j * k + i];                                            // T -= E^*
   }
   __syncthreads();
-  // D = W - U T2
-  tile_gemm(m, m, k, -1.0, U, k, 1, T2, m, 1, 1.0, W, mm, D, mm, sm);
+  tile_gemm(m, m, k, -1.0, U, k, 1, T, m, 1, 1.0, W, mm, D, mm, sm);          // D = W - U T
   // zero padding of D (rows/cols m .. mm-1)
   for (int idx = threadIdx.x; idx < mm * mm; idx += blockDim.x) {
     const int i = idx / mm, j = idx % mm;
@@ -145,8 +143,9 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
 //   y = 0: V^* Omega_tau      y = 1: U^* (Y_tau - D_tau Omega_tau)
 //   y = 2: U^* Psi_tau        y = 3: V^* (Z_tau - D_tau^* Psi_tau)
 // Child t writes rows [k t, k t + k) of the next level's panels (ld = s).
+template <int TK>
 __global__ void __launch_bounds__(kNT) parent_kernel(ParentArgs a) {
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmem<TK> sm;
   const int box = blockIdx.x, which = blockIdx.y;
   const int c0 = blockIdx.z * TN;
   const int m = a.mtau[box], k = a.k, s = a.s, mm = a.mmax;
@@ -182,7 +181,7 @@ __global__ void __launch_bounds__(kNT) apply_up_kernel(ApplyArgs a) {
   const double* Bas = a.B1 + (int64_t)box * a.mmax * k;
   const double* in = a.in + (a.leaf ? a.row0[box] : (int64_t)box * m) * a.ld_in;
   double* out = a.out + (int64_t)box * k * a.ld_out;
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmem<16> sm;
   tile_gemm(k, (int)a.nvec, m, 1.0, Bas, 1, k, in, a.ld_in, 1, 0.0, nullptr, 0, out, a.ld_out, sm);
 }
 
@@ -199,7 +198,7 @@ __global__ void __launch_bounds__(kNT) apply_down_kernel(ApplyArgs a) {
   const double* uh = a.in + (int64_t)box * k * a.ld_in;
   const double* qin = a.qin + rows * a.ld_q;
   double* out = a.out + rows * a.ld_out;
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmem<16> sm;
   // out = B uhat, then out += D qin (or D^* qin)
   tile_gemm(m, nv, k, 1.0, Bas, k, 1, uh, a.ld_in, 1, 0.0, nullptr, 0, out, a.ld_out, sm);
   if (a.transD)
@@ -212,7 +211,7 @@ __global__ void __launch_bounds__(kNT) apply_down_kernel(ApplyArgs a) {
 __global__ void __launch_bounds__(kNT) dense_small_kernel(const double* A, int64_t lda, int32_t transA,
                                                           const double* Bm, int64_t ldb, double* C, int64_t ldc,
                                                           int32_t M, int32_t N, int32_t K) {
-  __shared__ GemmSmem sm;
+  __shared__ GemmSmem<16> sm;
   const int r0 = blockIdx.x * 64;
   const int mrows = (M - r0) < 64 ? (M - r0) : 64;
   if (transA)
@@ -224,13 +223,21 @@ __global__ void __launch_bounds__(kNT) dense_small_kernel(const double* A, int64
 
 }  // namespace
 
+// Levels with few boxes are latency bound: deeper K chunks there.
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(combine_kernel, dim3(a.nodes), dim3(kNT), 0, st, a);
+  if (a.nodes < 256)
+    hipLaunchKernelGGL(combine_kernel<32>, dim3(a.nodes), dim3(kNT), 0, st, a);
+  else
+    hipLaunchKernelGGL(combine_kernel<16>, dim3(a.nodes), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_parent(const ParentArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(parent_kernel, dim3(a.nodes, 4, (a.s + TN - 1) / TN), dim3(kNT), 0, st, a);
+  const dim3 grid(a.nodes, 4, (a.s + TN - 1) / TN);
+  if (a.nodes < 256)
+    hipLaunchKernelGGL(parent_kernel<32>, grid, dim3(kNT), 0, st, a);
+  else
+    hipLaunchKernelGGL(parent_kernel<16>, grid, dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 

@@ -175,7 +175,7 @@ hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
   const int L = t->L;
   if (L == 0) {
     if (s < t->n) return HBS_EINVAL;
-    if (!hbs::side_supported((int)t->n, s, k, true)) return HBS_EUNSUPPORTED;
+    if (!hbs::side_supported((int)t->n, (int)t->n, s, k, true)) return HBS_EUNSUPPORTED;
     return HBS_OK;
   }
   int64_t mmin = INT64_MAX, mmax = 0;
@@ -187,9 +187,9 @@ hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
   if (mmin < k || s - mmax < k) return HBS_EINVAL;        // leaves
   if (L > 1 && s - 2 * (int64_t)k < k) return HBS_EINVAL;  // inner boxes of 2k rows
   if (s < 2 * (int64_t)k) return HBS_EINVAL;               // root
-  if (!hbs::side_supported((int)mmax, s, k, false)) return HBS_EUNSUPPORTED;
-  if (L > 1 && !hbs::side_supported(2 * k, s, k, false)) return HBS_EUNSUPPORTED;
-  if (!hbs::side_supported(2 * k, s, k, true)) return HBS_EUNSUPPORTED;
+  if (!hbs::side_supported((int)mmin, (int)mmax, s, k, false)) return HBS_EUNSUPPORTED;
+  if (L > 1 && !hbs::side_supported(2 * k, 2 * k, s, k, false)) return HBS_EUNSUPPORTED;
+  if (!hbs::side_supported(2 * k, 2 * k, s, k, true)) return HBS_EUNSUPPORTED;
   return HBS_OK;
 }
 

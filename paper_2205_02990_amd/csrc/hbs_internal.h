@@ -79,7 +79,7 @@ struct ApplyArgs {
   int32_t leaf;          // 1: rows addressed through row0 (finest level)
 };
 
-bool side_supported(int mmax, int s, int k, bool root);
+bool side_supported(int mmin, int mmax, int s, int k, bool root);
 hipError_t launch_side(const SideArgs& a, hipStream_t st);
 hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
 hipError_t launch_parent(const ParentArgs& a, hipStream_t st);
