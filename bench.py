@@ -34,18 +34,20 @@ def log(*a):
 # flop model (LAPACK operation counts of what one box computes)
 # --------------------------------------------------------------------------
 
-def side_flops(m, s, k, root=False):
-    """One side of one box: QR of the m x s test block (2 s m^2 - 2/3 m^3),
-    its m reflectors applied to the m x s sample block (4 m^2 s - 2 m^3), the
-    triangular solve for Y Omega^dagger (m^3), and - except at the root - the
-    truncated column-pivoted QR of the m x r sketch, r = s - m, stopped after k
-    steps (4 m r k - 2 (m + r) k^2 + 4/3 k^3) plus forming its m x k Q
+def lq_flops(m, s):
+    """One side of one box in the QR kernel: Householder QR of the m x s test
+    block (2 s m^2 - 2/3 m^3), its m reflectors applied to the m x s sample
+    block (4 m^2 s - 2 m^3), and the triangular solve for Y Omega^dagger (m^3)."""
+    return 2 * s * m * m - 2 * m ** 3 / 3 + 4 * m * m * s - 2 * m ** 3 + m ** 3
+
+
+def col_flops(m, s, k):
+    """One side of one box in the basis kernel: truncated column-pivoted QR of
+    the m x r sketch, r = s - m, stopped after k steps
+    (4 m r k - 2 (m + r) k^2 + 4/3 k^3), plus forming its m x k Q
     (2 m k^2 - 2/3 k^3)."""
-    f = 2 * s * m * m - 2 * m ** 3 / 3 + 4 * m * m * s - 2 * m ** 3 + m ** 3
-    if not root:
-        r = s - m
-        f += 4 * m * r * k - 2 * (m + r) * k * k + 4 * k ** 3 / 3 + 2 * m * k * k - 2 * k ** 3 / 3
-    return f
+    r = s - m
+    return 4 * m * r * k - 2 * (m + r) * k * k + 4 * k ** 3 / 3 + 2 * m * k * k - 2 * k ** 3 / 3
 
 
 def combine_flops(m, k):
@@ -60,31 +62,25 @@ def parent_flops(m, s, k):
 
 
 def sweep_model(leaf_sizes, k, s):
-    """Per-step flop totals by kernel class, and the side kernel's launch count."""
+    """Per-step flop totals by kernel class, algorithmic HBM bytes of the QR
+    kernel, and the launch count of each per-level kernel."""
     L = int(round(math.log2(len(leaf_sizes))))
-    side = comb = par = 0.0
-    launches = 0
+    lq = col = comb = par = 0.0
+    lq_bytes = 0
     for lev in range(L, 0, -1):
         ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
         for m in ms:
-            side += 2 * side_flops(m, s, k)
+            lq += 2 * lq_flops(m, s)
+            col += 2 * col_flops(m, s, k)
             comb += combine_flops(m, k)
             par += parent_flops(m, s, k)
-        launches += 1
-    root = side_flops(2 * k if L > 0 else leaf_sizes[0], s, k, root=True)
-    return {"side": side, "combine": comb, "parent": par, "root": root, "side_launches": launches}
-
-
-def sweep_bytes(leaf_sizes, k, s):
-    """Algorithmic HBM bytes of the side kernel per step: each side of each box
-    reads its two m x s panels and writes W (m x m) and its basis (m x k)."""
-    L = int(round(math.log2(len(leaf_sizes))))
-    b = 0
-    for lev in range(L, 0, -1):
-        ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
-        for m in ms:
-            b += 2 * 8 * (2 * m * s + m * m + m * k)
-    return b
+            # each side reads its two m x s panels, writes W (m x m) and the
+            # transposed m x (s - m) nullspace sketch
+            lq_bytes += 2 * 8 * (2 * m * s + m * m + m * (s - m))
+    m0 = 2 * k if L > 0 else leaf_sizes[0]
+    root = lq_flops(m0, s)
+    return {"lq": lq, "col": col, "combine": comb, "parent": par, "root": root, "launches": L,
+            "lq_bytes": lq_bytes}
 
 
 # --------------------------------------------------------------------------
@@ -171,14 +167,11 @@ def main():
     leaf_sizes = tree.leaf_sizes()
     f = hbs.Factors.create(tree, k, s, args.path)
 
-    # ---- warmup, then K timed sweeps ----------------------------------------
+    # ---- warmup, then K timed sweeps (the captured graph, as callers run it)
     for _ in range(args.warmup):
         f.compress_into(Omd, Yd, Psd, Zd)
     torch.cuda.synchronize()
     f.check()
-    f.profile(True)
-    f.profile_read()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record()
     for _ in range(args.steps):
@@ -187,13 +180,26 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
-    prof = f.profile_read()
-    f.profile(False)
     f.check()
     ms_per_step = gpu_ms / args.steps
     rows_per_s = n / (ms_per_step / 1e3)
     log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms), "
-        f"{rows_per_s:.4g} rows/s; kernel ms/step: " +
+        f"{rows_per_s:.4g} rows/s")
+
+    # ---- per-kernel device time: the same K sweeps launched directly, each
+    # launch bracketed by HIP events on the stream it runs on
+    f.profile(True)
+    f.profile_read()
+    e0.record()
+    for _ in range(args.steps):
+        f.compress_into(Omd, Yd, Psd, Zd)
+    e1.record()
+    torch.cuda.synchronize()
+    traced_ms = e0.elapsed_time(e1) / args.steps
+    prof = f.profile_read()
+    f.profile(False)
+    f.check()
+    log(f"traced pass {traced_ms:.3f} ms/step; kernel ms/step: " +
         ", ".join(f"{c} {v[0] / args.steps:.3f} ({v[1] // args.steps} launches)" for c, v in prof.items()))
 
     # ---- accuracy of the result against the black box ------------------------
@@ -204,25 +210,25 @@ def main():
     in_sample = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
     log(f"relative apply error vs the black box on 8 probes: {rel_err:.3e}; in-sample {in_sample:.3e}")
 
-    # ---- roofline of the dominant kernel (side kernel) -----------------------
+    # ---- roofline of the dominant kernel (the QR kernel, lq_kernel) ----------
     model = sweep_model(leaf_sizes, k, s)
-    side_ms, side_launches = prof["side"][0] / args.steps, prof["side"][1] / args.steps
-    side_tflops = model["side"] / (side_ms / 1e3) / 1e12
-    per_launch = model["side"] / model["side_launches"]
+    lq_ms, lq_launches = prof["lq"][0] / args.steps, prof["lq"][1] / args.steps
+    avg_launch_ms = lq_ms / lq_launches
+    per_launch = model["lq"] / model["launches"]
+    achieved = per_launch / (avg_launch_ms / 1e3) / 1e12
     traffic = None
     tfile = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                         f"side_kernel_{args.workload}_traffic.json")
+                         f"lq_kernel_{args.workload}_traffic.json")
     if os.path.exists(tfile):
         with open(tfile) as fh:
             tr = json.load(fh)
         if tr.get("source_digest") == _side_digest():
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": round(side_tflops, 3), "peak": round(PEAK_FP64_TFLOPS, 1),
-                "unit": "TFLOP/s", "frac": round(side_tflops / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "kernel": "side_kernel", "flops_per_launch": per_launch,
-                "avg_launch_ms": side_ms / side_launches,
-                "algorithmic_hbm_bytes_per_launch": sweep_bytes(leaf_sizes, k, s) / model["side_launches"]}
-    total_flops = model["side"] + model["combine"] + model["parent"] + model["root"]
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP64_TFLOPS, 1),
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+                "kernel": "lq_kernel", "flops_per_launch": per_launch, "avg_launch_ms": avg_launch_ms,
+                "algorithmic_hbm_bytes_per_launch": model["lq_bytes"] / model["launches"]}
+    total_flops = sum(model[c] for c in ("lq", "col", "combine", "parent", "root"))
 
     out = {
         "metric": METRIC, "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
@@ -234,6 +240,7 @@ def main():
         "rel_apply_err": rel_err, "in_sample_err": in_sample,
         "sampler_ms": sampler_ms, "rows_per_s_incl_sampler": n / ((ms_per_step + sampler_ms) / 1e3),
         "sweep_tflops_model": total_flops / (ms_per_step / 1e3) / 1e12,
+        "traced_ms_per_step": traced_ms,
         "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
     }
     if not args.no_cpu_baseline:

@@ -51,6 +51,7 @@ typedef enum {
 
 typedef struct hbs_tree hbs_tree;        /* host-only, immutable after create */
 typedef struct hbs_factors hbs_factors;  /* owns device memory                */
+typedef struct hbs_batch hbs_batch;      /* owns device memory of many sets  */
 
 /* Cluster tree of section 3.1 on the indices 0..n-1.  The root owns all of
  * them; a node [a, b) splits into [a, a + ceil((b-a)/2)) and [.., b); the
@@ -85,7 +86,9 @@ typedef struct {
  * tau needs m_tau >= k and s - m_tau >= k (the nullspace of its m_tau x s test
  * matrix must hold a k-column sketch); the root needs s >= its row count (2k,
  * or N when L = 0).  `prec` selects the arithmetic of the bulk products.
- * Allocation happens here, once; hbs_compress_into allocates nothing. */
+ * Device memory is allocated here, once; hbs_compress_into calls no
+ * hipMalloc (its first call captures the sweep as a HIP graph, later calls
+ * replay it). */
 hbs_status hbs_factors_create(const hbs_tree* t, int32_t k, int32_t s, hbs_precision prec,
                               hbs_factors** out);
 void       hbs_factors_destroy(hbs_factors* f);
@@ -107,6 +110,36 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
 hbs_status hbs_compress(const hbs_tree* t, int32_t k, int32_t s, const double* Omega, const double* Y,
                         const double* Psi, const double* Z, int64_t ld, hbs_precision prec,
                         void* hip_stream, hbs_factors** out);
+
+/* Many independent compressions in one sweep (section 4 applied to each
+ * matrix; the boxes of all of them at the same height above their leaves
+ * share each kernel launch).  Instance i has tree trees[i], rank k[i] and
+ * s[i] samples with the requirements of hbs_factors_create; instances of
+ * different (k, s) run in separate launches of the same step.  The trees are
+ * copied; *out is released with hbs_batch_destroy.  Device memory for every
+ * instance's factors and for the shared workspace is allocated here. */
+hbs_status hbs_batch_create(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
+                            hbs_precision prec, hbs_batch** out);
+void       hbs_batch_destroy(hbs_batch* b);
+/* Algorithm 2 for every instance: Omega[i], Y[i], Psi[i], Z[i] are HOST
+ * arrays of `count` device pointers to instance i's N_i x s_i panels with
+ * leading dimension ld[i] >= s_i (ld is a host array).  Same semantics as
+ * hbs_compress_into, per instance. */
+hbs_status hbs_batch_compress(hbs_batch* b, const double* const* Omega, const double* const* Y,
+                              const double* const* Psi, const double* const* Z, const int64_t* ld,
+                              void* hip_stream);
+/* A factor-set handle on instance i of the batch, usable with hbs_apply,
+ * hbs_level, hbs_root, hbs_check and hbs_profile (the last two act on the
+ * whole batch).  The instance's storage lives while the batch or any such
+ * handle does; release the handle with hbs_factors_destroy. */
+hbs_status hbs_batch_factors(hbs_batch* b, int32_t i, hbs_factors** out);
+/* hbs_batch_create, hbs_batch_compress, then one factor-set handle per
+ * instance written to out[0..count-1] (host array); the batch handle itself
+ * is released before returning. */
+hbs_status hbs_compress_batched(int32_t count, const hbs_tree* const* trees, const int32_t* k,
+                                const int32_t* s, const double* const* Omega, const double* const* Y,
+                                const double* const* Psi, const double* const* Z, const int64_t* ld,
+                                hbs_precision prec, void* hip_stream, hbs_factors** out);
 
 /* Algorithm 1: Out = A~ X (transpose = 0) or A~^* X (transpose != 0) for the
  * N x nvec block X; X and Out are N x nvec with leading dimension ldx >= nvec
@@ -137,15 +170,19 @@ hbs_status hbs_check(hbs_factors* f);
 const char* hbs_status_str(hbs_status s);
 
 /* Kernel timing of the sweep (tracing, off by default).  With `enable` != 0,
- * every later hbs_compress_into brackets each of its kernel launches with a
- * pair of HIP events on the caller's stream.  Kernel classes:
- *   0 side kernel (QR, nullspace sketch, solve, truncated QR: section 4.1-4.2)
- *   1 discrepancy block D_tau (eq. d_tau_formula)
- *   2 reduced samples for the parent level (eq. omega_tau_and_y_tau)
- *   3 root block D^(0) */
+ * every later sweep of the factor set's batch launches its kernels directly
+ * (not through the captured graph) and brackets each launch with a pair of
+ * HIP events on the caller's stream.  Kernel classes:
+ *   0 QR of the test blocks, reflectors applied to the samples and the
+ *     solve for Y_tau Omega_tau^dagger (sections 2.4, 4.1)
+ *   1 truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
+ *     (section 2.2, eqs. u_tau_formula, v_tau_formula)
+ *   2 discrepancy block D_tau (eq. d_tau_formula)
+ *   3 reduced samples for the parent level (eq. omega_tau_and_y_tau)
+ *   4 root block D^(0) */
 hbs_status hbs_profile(hbs_factors* f, int enable);
 /* Wait for the recorded work, then write the summed device time in ms and
- * the launch count of each class (arrays of nclass <= 4 entries, host
+ * the launch count of each class (arrays of nclass <= 5 entries, host
  * memory) accumulated since the previous read, and reset them. */
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass);
 

@@ -71,11 +71,13 @@ def synthetic_generators(rng: np.random.Generator, leaf_sizes, k: int) -> dict:
     """Random factors of an HBS matrix of exact block rank k.
 
     ``leaf_sizes`` lists the leaf sizes left to right (2^L of them, taken from
-    the caller's own cluster tree).  Draw order: every leaf left to right
-    (U, V, D), then every level L-1 .. 1 left to right (U, V, D), then the root
-    block.  Leaf U, V are m x k with orthonormal columns; inner U, V are
-    2k x k; every D is standard normal (m x m at leaves, 2k x 2k above); the
-    root block is 2k x 2k, or N x N when the tree is a single leaf.
+    the caller's own cluster tree).  Draw order, level by level from the
+    leaves (L) up to level 1: one Gaussian block for every U of the level,
+    one for every V, one for every D (nodes x m_max x m_max, node i keeping
+    its leading m_i x m_i part); then the root block.  Leaf U, V are m x k
+    with orthonormal columns; inner U, V are 2k x k; every D is standard
+    normal (m x m at leaves, 2k x 2k above); the root block is 2k x 2k, or
+    N x N when the tree is a single leaf.
     """
     leaf_sizes = [int(m) for m in leaf_sizes]
     nleaf = len(leaf_sizes)
@@ -86,20 +88,28 @@ def synthetic_generators(rng: np.random.Generator, leaf_sizes, k: int) -> dict:
     if L == 0:
         out["D0"] = gaussian(rng, leaf_sizes[0], leaf_sizes[0])
         return out
-    U, V, D = [], [], []
-    for m in leaf_sizes:
-        U.append(random_orthonormal(rng, m, k))
-        V.append(random_orthonormal(rng, m, k))
-        D.append(gaussian(rng, m, m))
-    out["U"][L], out["V"][L], out["D"][L] = U, V, D
-    for lev in range(L - 1, 0, -1):
-        U, V, D = [], [], []
-        for _ in range(2 ** lev):
-            U.append(random_orthonormal(rng, 2 * k, k))
-            V.append(random_orthonormal(rng, 2 * k, k))
-            D.append(gaussian(rng, 2 * k, 2 * k))
-        out["U"][lev], out["V"][lev], out["D"][lev] = U, V, D
+    for lev in range(L, 0, -1):
+        sizes = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
+        out["U"][lev] = _orthonormal_blocks(rng, sizes, k)
+        out["V"][lev] = _orthonormal_blocks(rng, sizes, k)
+        mm = max(sizes)
+        Dall = rng.standard_normal((len(sizes), mm, mm))
+        out["D"][lev] = [np.ascontiguousarray(Dall[i, :m, :m]) for i, m in enumerate(sizes)]
     out["D0"] = gaussian(rng, 2 * k, 2 * k)
+    return out
+
+
+def _orthonormal_blocks(rng, sizes, k):
+    """One (len(sizes), max(sizes), k) Gaussian draw; node i keeps its first
+    sizes[i] rows, whose columns are orthonormalised (batched per size)."""
+    mm = max(sizes)
+    G = rng.standard_normal((len(sizes), mm, k))
+    out = [None] * len(sizes)
+    for m in sorted(set(sizes)):
+        idx = [i for i, x in enumerate(sizes) if x == m]
+        q, _ = np.linalg.qr(G[idx, :m, :])
+        for j, i in enumerate(idx):
+            out[i] = np.ascontiguousarray(q[j])
     return out
 
 

@@ -108,16 +108,16 @@ __device__ void tile_gemm(int M, int N, int K, double alpha, const double* __res
 //   F = X U,  G = V^* F,  E = F - V G = (I - V V^*) X U,
 //   T = U^* W - E^*,  D = W - U T = (I - U U^*) W + U U^* ((I - V V^*) X)^*.
 template <int TK>
-__global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
+__global__ void __launch_bounds__(kNT) combine_kernel(SweepArgs a) {
   __shared__ GemmSmem<TK> sm;
-  const int box = blockIdx.x;
-  const int m = a.mtau[box], k = a.k, mm = a.mmax;
-  const double* U = a.U + (int64_t)box * mm * k;
-  const double* V = a.V + (int64_t)box * mm * k;
-  const double* W = a.W + (int64_t)box * mm * mm;
-  const double* X = a.X + (int64_t)box * mm * mm;
-  double* D = a.D + (int64_t)box * mm * mm;
-  double* F = a.T + (int64_t)box * (mm * mm + 3 * mm * k);  // m x k
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const int m = bx.m, k = a.k, mm = bx.dld;
+  const double* U = bx.U;
+  const double* V = bx.V;
+  const double* W = bx.W;
+  const double* X = bx.X;
+  double* D = bx.D;
+  double* F = bx.T;                                         // m x k
   double* Gm = F + mm * k;                                  // k x k
   double* E = Gm + mm * k;                                  // m x k
   double* T = E + mm * k;                                   // k x m
@@ -131,11 +131,6 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
   }
   __syncthreads();
   tile_gemm(m, m, k, -1.0, U, k, 1, T, m, 1, 1.0, W, mm, D, mm, sm);          // D = W - U T
-  // zero padding of D (rows/cols m .. mm-1)
-  for (int idx = threadIdx.x; idx < mm * mm; idx += blockDim.x) {
-    const int i = idx / mm, j = idx % mm;
-    if (i >= m || j >= m) D[idx] = 0.0;
-  }
 }
 
 // The four k x s blocks one child hands to its parent (eq.
@@ -144,27 +139,28 @@ __global__ void __launch_bounds__(kNT) combine_kernel(CombineArgs a) {
 //   y = 2: U^* Psi_tau        y = 3: V^* (Z_tau - D_tau^* Psi_tau)
 // Child t writes rows [k t, k t + k) of the next level's panels (ld = s).
 template <int TK>
-__global__ void __launch_bounds__(kNT) parent_kernel(ParentArgs a) {
+__global__ void __launch_bounds__(kNT) parent_kernel(SweepArgs a) {
   __shared__ GemmSmem<TK> sm;
-  const int box = blockIdx.x, which = blockIdx.y;
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const PanelSrc& ps = a.src[bx.src];
+  const int which = blockIdx.y;
   const int c0 = blockIdx.z * TN;
-  const int m = a.mtau[box], k = a.k, s = a.s, mm = a.mmax;
+  const int m = bx.m, k = a.k, s = a.s, mm = bx.dld;
   const int nc = (s - c0) < TN ? (s - c0) : TN;
-  const int64_t ld = a.ld;
-  const int64_t r0 = a.row0[box];
-  const double* U = a.U + (int64_t)box * mm * k;
-  const double* V = a.V + (int64_t)box * mm * k;
-  const double* D = a.D + (int64_t)box * mm * mm;
+  const int64_t ld = ps.ld;
+  const int64_t r0 = bx.row0;
+  const double* U = bx.U;
+  const double* V = bx.V;
+  const double* D = bx.D;
   const double* Bas = (which == 0 || which == 3) ? V : U;
-  const double* Tst = ((which < 2) ? a.Om : a.Ps) + r0 * ld + c0;
-  double* out = ((which == 0) ? a.nOm : (which == 1) ? a.nY : (which == 2) ? a.nPs : a.nZ) +
-                (int64_t)box * k * s + c0;
+  const double* Tst = ((which < 2) ? ps.Om : ps.Ps) + r0 * ld + c0;
+  double* out = ((which == 0) ? bx.nOm : (which == 1) ? bx.nY : (which == 2) ? bx.nPs : bx.nZ) + c0;
   if (which == 0 || which == 2) {
     tile_gemm(k, nc, m, 1.0, Bas, 1, k, Tst, ld, 1, 0.0, nullptr, 0, out, s, sm);
     return;
   }
-  const double* Smp = ((which == 1) ? a.Y : a.Z) + r0 * ld + c0;
-  double* R = a.R + ((int64_t)box * 2 + (which == 3)) * mm * s + c0;
+  const double* Smp = ((which == 1) ? ps.Y : ps.Z) + r0 * ld + c0;
+  double* R = bx.R + (int64_t)(which == 3) * m * s + c0;
   // R = Smp - D Tst  (D^* for the Z side)
   if (which == 1)
     tile_gemm(m, nc, m, -1.0, D, mm, 1, Tst, ld, 1, 1.0, Smp, ld, R, s, sm);
@@ -224,17 +220,17 @@ __global__ void __launch_bounds__(kNT) dense_small_kernel(const double* A, int64
 }  // namespace
 
 // Levels with few boxes are latency bound: deeper K chunks there.
-hipError_t launch_combine(const CombineArgs& a, hipStream_t st) {
-  if (a.nodes < 256)
-    hipLaunchKernelGGL(combine_kernel<32>, dim3(a.nodes), dim3(kNT), 0, st, a);
+hipError_t launch_combine(const SweepArgs& a, hipStream_t st) {
+  if (a.nboxes < 256)
+    hipLaunchKernelGGL(combine_kernel<32>, dim3(a.nboxes), dim3(kNT), 0, st, a);
   else
-    hipLaunchKernelGGL(combine_kernel<16>, dim3(a.nodes), dim3(kNT), 0, st, a);
+    hipLaunchKernelGGL(combine_kernel<16>, dim3(a.nboxes), dim3(kNT), 0, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_parent(const ParentArgs& a, hipStream_t st) {
-  const dim3 grid(a.nodes, 4, (a.s + TN - 1) / TN);
-  if (a.nodes < 256)
+hipError_t launch_parent(const SweepArgs& a, hipStream_t st) {
+  const dim3 grid(a.nboxes, 4, (a.s + TN - 1) / TN);
+  if (a.nboxes < 256)
     hipLaunchKernelGGL(parent_kernel<32>, grid, dim3(kNT), 0, st, a);
   else
     hipLaunchKernelGGL(parent_kernel<16>, grid, dim3(kNT), 0, st, a);

@@ -1,8 +1,13 @@
-// Host side of libhbs: cluster tree, factor storage, the level-by-level sweep
-// schedule of Algorithm 2, the apply of Algorithm 1, and argument checking.
+// Host side of libhbs: cluster trees, factor storage, the level-by-level sweep
+// schedule of Algorithm 2 (one set of launches per aligned level, shared by
+// every instance of a batch), its capture in a HIP graph, the apply of
+// Algorithm 1, and argument checking.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -17,13 +22,25 @@ struct hbs_tree {
 
 namespace {
 
+hbs_status from_hip(hipError_t e) {
+  if (e == hipSuccess) return HBS_OK;
+  if (e == hipErrorOutOfMemory) return HBS_ENOMEM;
+  return HBS_EDEVICE;
+}
+
+#define HIP_TRY(x)                             \
+  do {                                         \
+    hipError_t e_ = (x);                       \
+    if (e_ != hipSuccess) return from_hip(e_); \
+  } while (0)
+
 struct Level {
   int32_t nodes = 0, mmax = 0, mmin = 0;
   int32_t* mtau = nullptr;   // device [nodes]
-  int64_t* row0 = nullptr;   // device [nodes]: first row of each box in its panels
-  double* U = nullptr;       // device [nodes][mmax][k]
+  int64_t* row0 = nullptr;   // device [nodes]: leaf rows in the N-vector / 2k t above (apply)
+  double* U = nullptr;       // device [nodes][mmax][k], zero padded
   double* V = nullptr;
-  double* D = nullptr;       // device [nodes][mmax][mmax]
+  double* D = nullptr;       // device [nodes][mmax][mmax], zero padded
   // reduced test/sample panels consumed by this level's boxes (levels < L):
   // box t owns rows [2k t, 2k t + 2k), ld = s
   double* bOm = nullptr;
@@ -32,43 +49,68 @@ struct Level {
   double* bZ = nullptr;
 };
 
-hbs_status from_hip(hipError_t e) {
-  if (e == hipSuccess) return HBS_OK;
-  if (e == hipErrorOutOfMemory) return HBS_ENOMEM;
-  return HBS_EDEVICE;
-}
-
-}  // namespace
-
-struct hbs_factors {
+struct Instance {
   hbs_tree tree;
   int32_t k = 0, s = 0, L = 0;
-  hbs_precision prec = HBS_FP64;
-  std::vector<Level> lev;  // 0..L (level 0 holds the root's panels)
+  std::vector<Level> lev;  // 0..L
   double* D0 = nullptr;
   int32_t n0 = 0;
-  double* W = nullptr;
-  double* X = nullptr;
-  double* T = nullptr;
-  double* R = nullptr;
-  double* Bt = nullptr;
-  int32_t* flag = nullptr;
+  int src_in = -1;              // panel-source slot of the caller's inputs
+  std::vector<int> src_lev;     // panel-source slot of level l's reduced panels (l < L)
   // apply workspace
   double* qhat = nullptr;
   double* uhat = nullptr;
   int64_t apply_nvec = 0;
   std::vector<int64_t> hoff;  // row offset of level l's blocks in qhat/uhat
-  hipStream_t last = nullptr;
+};
+
+struct Launch {
+  hbs::SweepArgs args;
+};
+
+struct Mark {
+  hipEvent_t a, b;
+  int cls;
+};
+
+}  // namespace
+
+// A set of instances compressed together: one launch per aligned level and
+// (k, s) class covers the boxes of all of them.
+struct BatchImpl {
+  std::vector<Instance> inst;
   std::vector<void*> allocs;
-  // tracing: event pairs around launches (reused across sweeps)
+  hbs::PanelSrc* h_src = nullptr;  // pinned host copy of the panel-source table
+  hbs::PanelSrc* d_src = nullptr;
+  int nsrc = 0;
+  hbs::BoxDesc* d_box = nullptr;
+  std::vector<Launch> launches;
+  int32_t* flag = nullptr;
+  bool sweep_ready = false;  // workspace and launch plan exist
+  hipStream_t last = nullptr;
+  // graph of the whole sweep, captured on first use
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  hipStream_t cstream = nullptr;  // capture stream
+  // tracing
   bool prof = false;
-  struct Mark {
-    hipEvent_t a, b;
-    int cls;
-  };
   std::vector<Mark> marks;
   size_t nmarks = 0;
 
+  hipError_t alloc(void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipSuccess) allocs.push_back(*p);
+    return e;
+  }
+  void release(void* p) {
+    if (!p) return;
+    auto it = std::find(allocs.begin(), allocs.end(), p);
+    if (it == allocs.end()) return;
+    allocs.erase(it);
+    (void)hipFree(p);
+  }
   hipError_t mark_begin(int cls, hipStream_t st) {
     if (!prof) return hipSuccess;
     if (nmarks == marks.size()) {
@@ -85,90 +127,32 @@ struct hbs_factors {
     if (!prof) return hipSuccess;
     return hipEventRecord(marks[nmarks++].b, st);
   }
-
-  hipError_t alloc(void** p, size_t bytes) {
-    *p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMalloc(p, bytes);
-    if (e == hipSuccess) allocs.push_back(*p);
-    return e;
-  }
-  ~hbs_factors() {
+  ~BatchImpl() {
+    (void)hipDeviceSynchronize();
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (cstream) (void)hipStreamDestroy(cstream);
     for (Mark& m : marks) {
       (void)hipEventDestroy(m.a);
       (void)hipEventDestroy(m.b);
     }
+    if (h_src) (void)hipHostFree(h_src);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
 
-namespace {
+// The caller's batch handle: one more owner of the shared storage.
+struct hbs_batch {
+  std::shared_ptr<BatchImpl> b;
+};
 
-hbs_status build_levels(hbs_factors* f, bool with_workspace) {
-  const hbs_tree& t = f->tree;
-  const int L = t.L, k = f->k, s = f->s;
-  f->lev.assign(L + 1, Level{});
-  size_t wmax = 0, tmax = 0, rmax = 0, bmax = 0;
-  for (int l = 0; l <= L; ++l) {
-    Level& lv = f->lev[l];
-    lv.nodes = 1 << l;
-    std::vector<int32_t> mt(lv.nodes);
-    std::vector<int64_t> r0(lv.nodes);
-    if (l == L) {
-      for (int i = 0; i < lv.nodes; ++i) {
-        mt[i] = (int32_t)(t.start[l][i + 1] - t.start[l][i]);
-        r0[i] = t.start[l][i];
-      }
-    } else {
-      for (int i = 0; i < lv.nodes; ++i) {
-        mt[i] = 2 * k;
-        r0[i] = (int64_t)2 * k * i;
-      }
-    }
-    lv.mmax = *std::max_element(mt.begin(), mt.end());
-    lv.mmin = *std::min_element(mt.begin(), mt.end());
-    hipError_t e;
-    if ((e = f->alloc((void**)&lv.mtau, sizeof(int32_t) * lv.nodes)) != hipSuccess) return from_hip(e);
-    if ((e = f->alloc((void**)&lv.row0, sizeof(int64_t) * lv.nodes)) != hipSuccess) return from_hip(e);
-    if ((e = hipMemcpy(lv.mtau, mt.data(), sizeof(int32_t) * lv.nodes, hipMemcpyHostToDevice)) != hipSuccess)
-      return from_hip(e);
-    if ((e = hipMemcpy(lv.row0, r0.data(), sizeof(int64_t) * lv.nodes, hipMemcpyHostToDevice)) != hipSuccess)
-      return from_hip(e);
-    if (l >= 1) {
-      const size_t nb = (size_t)lv.nodes * lv.mmax * k * sizeof(double);
-      const size_t nd = (size_t)lv.nodes * lv.mmax * lv.mmax * sizeof(double);
-      if ((e = f->alloc((void**)&lv.U, nb)) != hipSuccess) return from_hip(e);
-      if ((e = f->alloc((void**)&lv.V, nb)) != hipSuccess) return from_hip(e);
-      if ((e = f->alloc((void**)&lv.D, nd)) != hipSuccess) return from_hip(e);
-      wmax = std::max(wmax, (size_t)lv.nodes * lv.mmax * lv.mmax);
-      tmax = std::max(tmax, (size_t)lv.nodes * ((size_t)lv.mmax * lv.mmax + 3 * (size_t)lv.mmax * k));
-      rmax = std::max(rmax, (size_t)lv.nodes * 2 * lv.mmax * s);
-      bmax = std::max(bmax, (size_t)lv.nodes * 2 * s * lv.mmax);
-    }
-    if (with_workspace && l < L) {
-      const size_t nb = (size_t)lv.nodes * 2 * k * s * sizeof(double);
-      if ((e = f->alloc((void**)&lv.bOm, nb)) != hipSuccess) return from_hip(e);
-      if ((e = f->alloc((void**)&lv.bY, nb)) != hipSuccess) return from_hip(e);
-      if ((e = f->alloc((void**)&lv.bPs, nb)) != hipSuccess) return from_hip(e);
-      if ((e = f->alloc((void**)&lv.bZ, nb)) != hipSuccess) return from_hip(e);
-    }
-  }
-  f->n0 = (L == 0) ? (int32_t)t.n : 2 * k;
-  hipError_t e;
-  if ((e = f->alloc((void**)&f->D0, sizeof(double) * (size_t)f->n0 * f->n0)) != hipSuccess) return from_hip(e);
-  if ((e = f->alloc((void**)&f->flag, sizeof(int32_t))) != hipSuccess) return from_hip(e);
-  if ((e = hipMemset(f->flag, 0, sizeof(int32_t))) != hipSuccess) return from_hip(e);
-  if (with_workspace) {
-    if ((e = f->alloc((void**)&f->W, sizeof(double) * wmax)) != hipSuccess) return from_hip(e);
-    if ((e = f->alloc((void**)&f->X, sizeof(double) * wmax)) != hipSuccess) return from_hip(e);
-    if ((e = f->alloc((void**)&f->T, sizeof(double) * tmax)) != hipSuccess) return from_hip(e);
-    if ((e = f->alloc((void**)&f->R, sizeof(double) * rmax)) != hipSuccess) return from_hip(e);
-    if ((e = f->alloc((void**)&f->Bt, sizeof(double) * bmax)) != hipSuccess) return from_hip(e);
-  }
-  f->hoff.assign(L + 2, 0);
-  for (int l = 1; l <= L; ++l) f->hoff[l + 1] = f->hoff[l] + (int64_t)(1 << l) * k;
-  return HBS_OK;
-}
+// A factor set is a handle on one instance of a batch (a batch of one for
+// hbs_compress); the storage lives while the batch or any handle does.
+struct hbs_factors {
+  std::shared_ptr<BatchImpl> b;
+  int idx = 0;
+};
+
+namespace {
 
 hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
   if (!t || k < 1 || s < 1) return HBS_EINVAL;
@@ -193,11 +177,266 @@ hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
   return HBS_OK;
 }
 
-#define HIP_TRY(x)                                \
-  do {                                            \
-    hipError_t e_ = (x);                          \
-    if (e_ != hipSuccess) return from_hip(e_);    \
-  } while (0)
+// Factor storage (and, for a compressible batch, the reduced panels) of one instance.
+hbs_status build_instance(BatchImpl* b, Instance& in, bool with_panels) {
+  const hbs_tree& t = in.tree;
+  const int L = t.L, k = in.k, s = in.s;
+  in.L = L;
+  in.lev.assign(L + 1, Level{});
+  for (int l = 0; l <= L; ++l) {
+    Level& lv = in.lev[l];
+    lv.nodes = 1 << l;
+    std::vector<int32_t> mt(lv.nodes);
+    std::vector<int64_t> r0(lv.nodes);
+    for (int i = 0; i < lv.nodes; ++i) {
+      if (l == L) {
+        mt[i] = (int32_t)(t.start[l][i + 1] - t.start[l][i]);
+        r0[i] = t.start[l][i];
+      } else {
+        mt[i] = 2 * k;
+        r0[i] = (int64_t)2 * k * i;
+      }
+    }
+    lv.mmax = *std::max_element(mt.begin(), mt.end());
+    lv.mmin = *std::min_element(mt.begin(), mt.end());
+    HIP_TRY(b->alloc((void**)&lv.mtau, sizeof(int32_t) * lv.nodes));
+    HIP_TRY(b->alloc((void**)&lv.row0, sizeof(int64_t) * lv.nodes));
+    HIP_TRY(hipMemcpy(lv.mtau, mt.data(), sizeof(int32_t) * lv.nodes, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(lv.row0, r0.data(), sizeof(int64_t) * lv.nodes, hipMemcpyHostToDevice));
+    if (l >= 1) {
+      const size_t nb = (size_t)lv.nodes * lv.mmax * k * sizeof(double);
+      const size_t nd = (size_t)lv.nodes * lv.mmax * lv.mmax * sizeof(double);
+      HIP_TRY(b->alloc((void**)&lv.U, nb));
+      HIP_TRY(b->alloc((void**)&lv.V, nb));
+      HIP_TRY(b->alloc((void**)&lv.D, nd));
+      // padding rows/columns past m_tau stay zero: the kernels write only m_tau x k and m_tau x m_tau
+      HIP_TRY(hipMemset(lv.U, 0, nb));
+      HIP_TRY(hipMemset(lv.V, 0, nb));
+      HIP_TRY(hipMemset(lv.D, 0, nd));
+    }
+    if (with_panels && l < L) {
+      const size_t nb = (size_t)lv.nodes * 2 * k * s * sizeof(double);
+      HIP_TRY(b->alloc((void**)&lv.bOm, nb));
+      HIP_TRY(b->alloc((void**)&lv.bY, nb));
+      HIP_TRY(b->alloc((void**)&lv.bPs, nb));
+      HIP_TRY(b->alloc((void**)&lv.bZ, nb));
+    }
+  }
+  in.n0 = (L == 0) ? (int32_t)t.n : 2 * k;
+  HIP_TRY(b->alloc((void**)&in.D0, sizeof(double) * (size_t)in.n0 * in.n0));
+  in.hoff.assign(L + 2, 0);
+  for (int l = 1; l <= L; ++l) in.hoff[l + 1] = in.hoff[l] + (int64_t)(1 << l) * k;
+  return HBS_OK;
+}
+
+// Launch plan and workspace of the sweep: box descriptors for every aligned
+// level and (k, s) class, built once.
+hbs_status build_sweep(BatchImpl* b) {
+  HIP_TRY(hbs::prepare_side_kernels());
+  // panel-source slots: each instance's inputs, then its levels' reduced panels
+  int nsrc = 0;
+  for (Instance& in : b->inst) {
+    in.src_in = nsrc++;
+    in.src_lev.assign(in.L, -1);
+    for (int l = 0; l < in.L; ++l) in.src_lev[l] = nsrc++;
+  }
+  b->nsrc = nsrc;
+  HIP_TRY(hipHostMalloc((void**)&b->h_src, sizeof(hbs::PanelSrc) * nsrc, hipHostMallocDefault));
+  std::memset(b->h_src, 0, sizeof(hbs::PanelSrc) * nsrc);
+  for (Instance& in : b->inst)
+    for (int l = 0; l < in.L; ++l)
+      b->h_src[in.src_lev[l]] = hbs::PanelSrc{in.lev[l].bOm, in.lev[l].bY, in.lev[l].bPs, in.lev[l].bZ, in.s};
+  HIP_TRY(b->alloc((void**)&b->d_src, sizeof(hbs::PanelSrc) * nsrc));
+
+  int maxL = 0;
+  for (const Instance& in : b->inst) maxL = std::max(maxL, in.L);
+  std::map<std::pair<int, int>, int> cls;  // (k, s) classes
+  for (const Instance& in : b->inst) cls.emplace(std::make_pair(in.k, in.s), 0);
+  // box lists per (step, class); step j handles level L_i - j of instance i,
+  // the last step every root
+  struct Group {
+    int k, s;
+    bool root;
+    std::vector<hbs::BoxDesc> boxes;
+    std::vector<size_t> ws;  // workspace doubles needed by each box
+  };
+  std::vector<std::vector<Group>> steps(maxL + 1);
+  for (int j = 0; j <= maxL; ++j)
+    for (auto& c : cls) steps[j].push_back(Group{c.first.first, c.first.second, j == maxL, {}, {}});
+  auto group_of = [&](int j, const Instance& in) -> Group& {
+    for (Group& g : steps[j])
+      if (g.k == in.k && g.s == in.s) return g;
+    return steps[j][0];
+  };
+  for (Instance& in : b->inst) {
+    const int k = in.k, s = in.s;
+    const hbs_tree& t = in.tree;
+    for (int l = in.L; l >= 1; --l) {
+      Level& lv = in.lev[l];
+      Level& up = in.lev[l - 1];
+      Group& g = group_of(in.L - l, in);
+      for (int i = 0; i < lv.nodes; ++i) {
+        hbs::BoxDesc d{};
+        d.src = (l == in.L) ? in.src_in : in.src_lev[l];
+        d.row0 = (l == in.L) ? t.start[l][i] : (int64_t)2 * k * i;
+        d.m = (l == in.L) ? (int32_t)(t.start[l][i + 1] - t.start[l][i]) : 2 * k;
+        d.dld = lv.mmax;
+        d.U = lv.U + (size_t)i * lv.mmax * k;
+        d.V = lv.V + (size_t)i * lv.mmax * k;
+        d.D = lv.D + (size_t)i * lv.mmax * lv.mmax;
+        d.nOm = up.bOm + (size_t)k * i * s;
+        d.nY = up.bY + (size_t)k * i * s;
+        d.nPs = up.bPs + (size_t)k * i * s;
+        d.nZ = up.bZ + (size_t)k * i * s;
+        const size_t dl = lv.mmax;
+        g.boxes.push_back(d);
+        g.ws.push_back(3 * dl * dl + 3 * dl * k + 4 * dl * s);
+      }
+    }
+    hbs::BoxDesc d{};
+    d.src = (in.L == 0) ? in.src_in : in.src_lev[0];
+    d.row0 = 0;
+    d.m = in.n0;
+    d.dld = in.n0;
+    d.D = in.D0;
+    group_of(maxL, in).boxes.push_back(d);
+    group_of(maxL, in).ws.push_back(0);
+  }
+  // workspace: steps run one after another, so one pool sized for the largest step
+  size_t wsmax = 0, nbox = 0;
+  for (auto& st : steps) {
+    size_t w = 0;
+    for (Group& g : st) {
+      for (size_t x : g.ws) w += x;
+      nbox += g.boxes.size();
+    }
+    wsmax = std::max(wsmax, w);
+  }
+  double* ws = nullptr;
+  HIP_TRY(b->alloc((void**)&ws, sizeof(double) * std::max<size_t>(wsmax, 1)));
+  HIP_TRY(b->alloc((void**)&b->d_box, sizeof(hbs::BoxDesc) * std::max<size_t>(nbox, 1)));
+  std::vector<hbs::BoxDesc> all;
+  all.reserve(nbox);
+  for (int j = 0; j <= maxL; ++j) {
+    size_t off = 0;  // the groups of one step share the pool
+    for (Group& g : steps[j]) {
+      if (g.boxes.empty()) continue;
+      const size_t first = all.size();
+      int mmax = 0, mmin = INT_MAX;
+      for (size_t q = 0; q < g.boxes.size(); ++q) {
+        hbs::BoxDesc d = g.boxes[q];
+        if (!g.root) {
+          const size_t dl = d.dld, kk = g.k, ss = g.s;
+          d.W = ws + off;
+          d.X = d.W + dl * dl;
+          d.T = d.X + dl * dl;
+          d.Bt = d.T + dl * dl + 3 * dl * kk;
+          d.R = d.Bt + 2 * ss * dl;
+          off += g.ws[q];
+        }
+        mmax = std::max(mmax, d.m);
+        mmin = std::min(mmin, d.m);
+        all.push_back(d);
+      }
+      Launch ln{};
+      ln.args.box = b->d_box + first;
+      ln.args.src = b->d_src;
+      ln.args.nboxes = (int32_t)g.boxes.size();
+      ln.args.k = g.k;
+      ln.args.s = g.s;
+      ln.args.mmax = mmax;
+      ln.args.mmin = mmin;
+      ln.args.root = g.root ? 1 : 0;
+      ln.args.flag = b->flag;
+      b->launches.push_back(ln);
+    }
+  }
+  HIP_TRY(hipMemcpy(b->d_box, all.data(), sizeof(hbs::BoxDesc) * all.size(), hipMemcpyHostToDevice));
+  b->sweep_ready = true;
+  return HBS_OK;
+}
+
+hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
+  for (const Launch& ln : b->launches) {
+    HIP_TRY(b->mark_begin(ln.args.root ? 4 : 0, st));
+    HIP_TRY(hbs::launch_lq(ln.args, st));
+    HIP_TRY(b->mark_end(st));
+    if (ln.args.root) continue;
+    HIP_TRY(b->mark_begin(1, st));
+    HIP_TRY(hbs::launch_col(ln.args, st));
+    HIP_TRY(b->mark_end(st));
+    HIP_TRY(b->mark_begin(2, st));
+    HIP_TRY(hbs::launch_combine(ln.args, st));
+    HIP_TRY(b->mark_end(st));
+    HIP_TRY(b->mark_begin(3, st));
+    HIP_TRY(hbs::launch_parent(ln.args, st));
+    HIP_TRY(b->mark_end(st));
+  }
+  return HBS_OK;
+}
+
+// Point the panel-source slots at the caller's inputs, then run the sweep:
+// replay of the captured graph, or direct launches while tracing.
+hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(b->d_src, b->h_src, sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st));
+  b->last = st;
+  if (b->prof || !b->use_graph) return enqueue_sweep(b, st);
+  if (!b->gexec) {
+    // captured once on a private stream (the default stream cannot be
+    // captured); the graph then replays on whatever stream the caller passes
+    if (!b->cstream) HIP_TRY(hipStreamCreateWithFlags(&b->cstream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(b->cstream, hipStreamCaptureModeThreadLocal));
+    hbs_status s1 = enqueue_sweep(b, b->cstream);
+    hipError_t e = hipStreamEndCapture(b->cstream, &g);
+    if (s1 != HBS_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s1;
+    }
+    HIP_TRY(e);
+    e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(e);
+  }
+  HIP_TRY(hipGraphLaunch(b->gexec, st));
+  return HBS_OK;
+}
+
+hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
+                      hbs_precision prec, bool with_sweep, std::shared_ptr<BatchImpl>* out) {
+  if (count < 1 || !trees || !k || (with_sweep && !s)) return HBS_EINVAL;
+  if (prec != HBS_FP64) return HBS_EUNSUPPORTED;
+  for (int i = 0; i < count; ++i) {
+    if (with_sweep) {
+      hbs_status st = check_shape(trees[i], k[i], s[i]);
+      if (st != HBS_OK) return st;
+    } else if (!trees[i] || k[i] < 1) {
+      return HBS_EINVAL;
+    }
+  }
+  std::shared_ptr<BatchImpl> b(new (std::nothrow) BatchImpl);
+  if (!b) return HBS_ENOMEM;
+  HIP_TRY(b->alloc((void**)&b->flag, sizeof(int32_t)));
+  HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));
+  b->inst.resize(count);
+  for (int i = 0; i < count; ++i) {
+    Instance& in = b->inst[i];
+    in.tree = *trees[i];
+    in.k = k[i];
+    in.s = with_sweep ? s[i] : 0;
+    hbs_status st = build_instance(b.get(), in, with_sweep);
+    if (st != HBS_OK) return st;
+  }
+  if (with_sweep) {
+    hbs_status st = build_sweep(b.get());
+    if (st != HBS_OK) return st;
+  }
+  *out = b;
+  return HBS_OK;
+}
+
+Instance& inst_of(const hbs_factors* f) { return f->b->inst[f->idx]; }
+
 
 }  // namespace
 
@@ -237,14 +476,14 @@ hbs_status hbs_tree_create(int64_t n, int32_t leaf_max, hbs_tree** out) {
     nxt.reserve(2 * cur.size() - 1);
     nxt.push_back(0);
     for (size_t i = 0; i + 1 < cur.size(); ++i) {
-      const int64_t a = cur[i], b = cur[i + 1];
-      const int64_t half = (b - a + 1) / 2;  // ceil((b - a) / 2)
-      if (half == 0 || b - a - half == 0) {
+      const int64_t a = cur[i], bb = cur[i + 1];
+      const int64_t half = (bb - a + 1) / 2;  // ceil((b - a) / 2)
+      if (half == 0 || bb - a - half == 0) {
         delete t;
         return HBS_EINVAL;  // empty child
       }
       nxt.push_back(a + half);
-      nxt.push_back(b);
+      nxt.push_back(bb);
     }
     t->start.push_back(std::move(nxt));
   }
@@ -268,128 +507,28 @@ hbs_status hbs_tree_node(const hbs_tree* t, int32_t level, int64_t node, int64_t
 hbs_status hbs_factors_create(const hbs_tree* t, int32_t k, int32_t s, hbs_precision prec, hbs_factors** out) {
   if (!out) return HBS_EINVAL;
   *out = nullptr;
-  hbs_status st = check_shape(t, k, s);
+  std::shared_ptr<BatchImpl> b;
+  hbs_status st = make_batch(1, &t, &k, &s, prec, true, &b);
   if (st != HBS_OK) return st;
-  if (prec != HBS_FP64) return HBS_EUNSUPPORTED;
   hbs_factors* f = new (std::nothrow) hbs_factors;
   if (!f) return HBS_ENOMEM;
-  f->tree = *t;
-  f->k = k;
-  f->s = s;
-  f->L = t->L;
-  f->prec = prec;
-  st = build_levels(f, true);
-  if (st != HBS_OK) {
-    delete f;
-    return st;
-  }
+  f->b = b;
+  f->idx = 0;
   *out = f;
   return HBS_OK;
 }
 
-void hbs_factors_destroy(hbs_factors* f) {
-  if (f) (void)hipDeviceSynchronize();
-  delete f;
-}
+void hbs_factors_destroy(hbs_factors* f) { delete f; }
 
 hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* Y, const double* Psi,
                              const double* Z, int64_t ld, void* hip_stream) {
-  if (!f || !Omega || !Y || !Psi || !Z || ld < f->s) return HBS_EINVAL;
-  if (!f->W) return HBS_EINVAL;  // imported factor sets have no sweep workspace
-  hipStream_t st = (hipStream_t)hip_stream;
-  f->last = st;
-  const int L = f->L, k = f->k, s = f->s;
-  for (int l = L; l >= 1; --l) {
-    Level& lv = f->lev[l];
-    Level& up = f->lev[l - 1];
-    const bool leaf = (l == L);
-    hbs::SideArgs sa{};
-    sa.Om = leaf ? Omega : lv.bOm;
-    sa.Y = leaf ? Y : lv.bY;
-    sa.Ps = leaf ? Psi : lv.bPs;
-    sa.Z = leaf ? Z : lv.bZ;
-    sa.ld = leaf ? ld : s;
-    sa.row0 = lv.row0;
-    sa.mtau = lv.mtau;
-    sa.nodes = lv.nodes;
-    sa.s = s;
-    sa.k = k;
-    sa.mmax = lv.mmax;
-    sa.mmin = lv.mmin;
-    sa.U = lv.U;
-    sa.V = lv.V;
-    sa.W = f->W;
-    sa.X = f->X;
-    sa.Bt = f->Bt;
-    sa.flag = f->flag;
-    sa.root = 0;
-    HIP_TRY(f->mark_begin(0, st));
-    HIP_TRY(hbs::launch_side(sa, st));
-    HIP_TRY(f->mark_end(st));
-    hbs::CombineArgs ca{};
-    ca.mtau = lv.mtau;
-    ca.nodes = lv.nodes;
-    ca.k = k;
-    ca.mmax = lv.mmax;
-    ca.U = lv.U;
-    ca.V = lv.V;
-    ca.W = f->W;
-    ca.X = f->X;
-    ca.D = lv.D;
-    ca.T = f->T;
-    HIP_TRY(f->mark_begin(1, st));
-    HIP_TRY(hbs::launch_combine(ca, st));
-    HIP_TRY(f->mark_end(st));
-    hbs::ParentArgs pa{};
-    pa.Om = sa.Om;
-    pa.Y = sa.Y;
-    pa.Ps = sa.Ps;
-    pa.Z = sa.Z;
-    pa.ld = sa.ld;
-    pa.row0 = lv.row0;
-    pa.mtau = lv.mtau;
-    pa.nodes = lv.nodes;
-    pa.s = s;
-    pa.k = k;
-    pa.mmax = lv.mmax;
-    pa.U = lv.U;
-    pa.V = lv.V;
-    pa.D = lv.D;
-    pa.R = f->R;
-    pa.nOm = up.bOm;
-    pa.nY = up.bY;
-    pa.nPs = up.bPs;
-    pa.nZ = up.bZ;
-    HIP_TRY(f->mark_begin(2, st));
-    HIP_TRY(hbs::launch_parent(pa, st));
-    HIP_TRY(f->mark_end(st));
-  }
-  // root: D^(0) = Y_root Omega_root^dagger
-  Level& rt = f->lev[0];
-  hbs::SideArgs sa{};
-  sa.Om = (L == 0) ? Omega : rt.bOm;
-  sa.Y = (L == 0) ? Y : rt.bY;
-  sa.Ps = sa.Om;
-  sa.Z = sa.Y;
-  sa.ld = (L == 0) ? ld : s;
-  sa.row0 = rt.row0;
-  sa.mtau = rt.mtau;
-  sa.nodes = 1;
-  sa.s = s;
-  sa.k = k;
-  sa.mmax = f->n0;
-  sa.mmin = f->n0;
-  sa.U = nullptr;
-  sa.V = nullptr;
-  sa.W = f->D0;
-  sa.X = f->D0;
-  sa.Bt = nullptr;
-  sa.flag = f->flag;
-  sa.root = 1;
-  HIP_TRY(f->mark_begin(3, st));
-  HIP_TRY(hbs::launch_side(sa, st));
-  HIP_TRY(f->mark_end(st));
-  return HBS_OK;
+  if (!f || !Omega || !Y || !Psi || !Z) return HBS_EINVAL;
+  BatchImpl* b = f->b.get();
+  if (!b->sweep_ready || b->inst.size() != 1) return HBS_EINVAL;  // imported sets, batch members
+  Instance& in = b->inst[0];
+  if (ld < in.s) return HBS_EINVAL;
+  b->h_src[in.src_in] = hbs::PanelSrc{Omega, Y, Psi, Z, ld};
+  return run_sweep(b, (hipStream_t)hip_stream);
 }
 
 hbs_status hbs_compress(const hbs_tree* t, int32_t k, int32_t s, const double* Omega, const double* Y,
@@ -410,33 +549,101 @@ hbs_status hbs_compress(const hbs_tree* t, int32_t k, int32_t s, const double* O
   return HBS_OK;
 }
 
+hbs_status hbs_batch_create(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
+                            hbs_precision prec, hbs_batch** out) {
+  if (!out) return HBS_EINVAL;
+  *out = nullptr;
+  std::shared_ptr<BatchImpl> b;
+  hbs_status st = make_batch(count, trees, k, s, prec, true, &b);
+  if (st != HBS_OK) return st;
+  hbs_batch* h = new (std::nothrow) hbs_batch;
+  if (!h) return HBS_ENOMEM;
+  h->b = b;
+  *out = h;
+  return HBS_OK;
+}
+
+void hbs_batch_destroy(hbs_batch* h) { delete h; }
+
+hbs_status hbs_batch_compress(hbs_batch* h, const double* const* Omega, const double* const* Y,
+                              const double* const* Psi, const double* const* Z, const int64_t* ld,
+                              void* hip_stream) {
+  if (!h || !Omega || !Y || !Psi || !Z || !ld) return HBS_EINVAL;
+  BatchImpl* b = h->b.get();
+  for (size_t i = 0; i < b->inst.size(); ++i) {
+    Instance& in = b->inst[i];
+    if (!Omega[i] || !Y[i] || !Psi[i] || !Z[i] || ld[i] < in.s) return HBS_EINVAL;
+  }
+  for (size_t i = 0; i < b->inst.size(); ++i)
+    b->h_src[b->inst[i].src_in] = hbs::PanelSrc{Omega[i], Y[i], Psi[i], Z[i], ld[i]};
+  return run_sweep(b, (hipStream_t)hip_stream);
+}
+
+hbs_status hbs_batch_factors(hbs_batch* h, int32_t i, hbs_factors** out) {
+  if (!h || !out) return HBS_EINVAL;
+  *out = nullptr;
+  const std::shared_ptr<BatchImpl>& b = h->b;
+  if (i < 0 || i >= (int32_t)b->inst.size()) return HBS_EINVAL;
+  hbs_factors* f = new (std::nothrow) hbs_factors;
+  if (!f) return HBS_ENOMEM;
+  f->b = b;
+  f->idx = i;
+  *out = f;
+  return HBS_OK;
+}
+
+hbs_status hbs_compress_batched(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
+                                const double* const* Omega, const double* const* Y, const double* const* Psi,
+                                const double* const* Z, const int64_t* ld, hbs_precision prec, void* hip_stream,
+                                hbs_factors** out) {
+  if (!out || count < 1) return HBS_EINVAL;
+  for (int i = 0; i < count; ++i) out[i] = nullptr;
+  hbs_batch* h = nullptr;
+  hbs_status st = hbs_batch_create(count, trees, k, s, prec, &h);
+  if (st != HBS_OK) return st;
+  st = hbs_batch_compress(h, Omega, Y, Psi, Z, ld, hip_stream);
+  for (int i = 0; st == HBS_OK && i < count; ++i) st = hbs_batch_factors(h, i, &out[i]);
+  if (st != HBS_OK)
+    for (int i = 0; i < count; ++i) {
+      hbs_factors_destroy(out[i]);
+      out[i] = nullptr;
+    }
+  hbs_batch_destroy(h);
+  return st;
+}
+
 hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* Out, int64_t nvec, int64_t ldx,
                      void* hip_stream) {
   if (!f || !Xin || !Out || nvec < 1 || ldx < nvec) return HBS_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
-  f->last = st;
-  const int L = f->L, k = f->k;
+  Instance& in = inst_of(f);
+  f->b->last = st;
+  const int L = in.L, k = in.k;
   if (L == 0) {
-    HIP_TRY(hbs::launch_dense_small(f->D0, f->n0, transpose ? 1 : 0, Xin, ldx, Out, ldx, f->n0, (int)nvec, f->n0,
+    HIP_TRY(hbs::launch_dense_small(in.D0, in.n0, transpose ? 1 : 0, Xin, ldx, Out, ldx, in.n0, (int)nvec, in.n0,
                                     st));
     return HBS_OK;
   }
-  if (nvec > f->apply_nvec) {
+  if (nvec > in.apply_nvec) {
     HIP_TRY(hipStreamSynchronize(st));
-    const size_t rows = (size_t)f->hoff[L + 1];
+    const size_t rows = (size_t)in.hoff[L + 1];
     void* q = nullptr;
     void* u = nullptr;
-    HIP_TRY(f->alloc(&q, sizeof(double) * rows * nvec));
-    HIP_TRY(f->alloc(&u, sizeof(double) * rows * nvec));
-    f->qhat = (double*)q;
-    f->uhat = (double*)u;
-    f->apply_nvec = nvec;
+    f->b->release(in.qhat);
+    f->b->release(in.uhat);
+    in.qhat = in.uhat = nullptr;
+    in.apply_nvec = 0;
+    HIP_TRY(f->b->alloc(&q, sizeof(double) * rows * nvec));
+    HIP_TRY(f->b->alloc(&u, sizeof(double) * rows * nvec));
+    in.qhat = (double*)q;
+    in.uhat = (double*)u;
+    in.apply_nvec = nvec;
   }
-  auto qh = [&](int l) { return f->qhat + f->hoff[l] * nvec; };
-  auto uh = [&](int l) { return f->uhat + f->hoff[l] * nvec; };
+  auto qh = [&](int l) { return in.qhat + in.hoff[l] * nvec; };
+  auto uh = [&](int l) { return in.uhat + in.hoff[l] * nvec; };
   // upward pass
   for (int l = L; l >= 1; --l) {
-    Level& lv = f->lev[l];
+    Level& lv = in.lev[l];
     hbs::ApplyArgs a{};
     a.mtau = lv.mtau;
     a.row0 = lv.row0;
@@ -453,11 +660,11 @@ hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* O
     HIP_TRY(hbs::launch_apply_up(a, st));
   }
   // root block
-  HIP_TRY(hbs::launch_dense_small(f->D0, f->n0, transpose ? 1 : 0, qh(1), nvec, uh(1), nvec, f->n0, (int)nvec,
-                                  f->n0, st));
+  HIP_TRY(hbs::launch_dense_small(in.D0, in.n0, transpose ? 1 : 0, qh(1), nvec, uh(1), nvec, in.n0, (int)nvec,
+                                  in.n0, st));
   // downward pass
   for (int l = 1; l <= L; ++l) {
-    Level& lv = f->lev[l];
+    Level& lv = in.lev[l];
     hbs::ApplyArgs a{};
     a.mtau = lv.mtau;
     a.row0 = lv.row0;
@@ -485,52 +692,42 @@ hbs_status hbs_factors_import(const hbs_tree* t, int32_t k, const hbs_level_view
   if (!out) return HBS_EINVAL;
   *out = nullptr;
   if (!t || k < 1 || !D0 || (t->L > 0 && !levels)) return HBS_EINVAL;
-  hbs_factors* f = new (std::nothrow) hbs_factors;
-  if (!f) return HBS_ENOMEM;
-  f->tree = *t;
-  f->k = k;
-  f->s = 0;
-  f->L = t->L;
-  hbs_status st = build_levels(f, false);
-  if (st != HBS_OK) {
-    delete f;
-    return st;
-  }
+  std::shared_ptr<BatchImpl> b;
+  int32_t s0 = 0;
+  hbs_status st = make_batch(1, &t, &k, &s0, HBS_FP64, false, &b);
+  if (st != HBS_OK) return st;
+  Instance& in = b->inst[0];
   hipStream_t hs = (hipStream_t)hip_stream;
-  for (int l = 1; l <= f->L; ++l) {
+  for (int l = 1; l <= in.L; ++l) {
     const hbs_level_view& v = levels[l - 1];
-    Level& lv = f->lev[l];
-    if (v.level != l || v.nodes != lv.nodes || v.m != lv.mmax || v.k != k || !v.U || !v.V || !v.D) {
-      delete f;
+    Level& lv = in.lev[l];
+    if (v.level != l || v.nodes != lv.nodes || v.m != lv.mmax || v.k != k || !v.U || !v.V || !v.D)
       return HBS_EINVAL;
-    }
     const size_t nb = (size_t)lv.nodes * lv.mmax * k * sizeof(double);
     const size_t nd = (size_t)lv.nodes * lv.mmax * lv.mmax * sizeof(double);
-    hipError_t e = hipMemcpyAsync(lv.U, v.U, nb, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(lv.V, v.V, nb, hipMemcpyDeviceToDevice, hs);
-    if (e == hipSuccess) e = hipMemcpyAsync(lv.D, v.D, nd, hipMemcpyDeviceToDevice, hs);
-    if (e != hipSuccess) {
-      delete f;
-      return from_hip(e);
-    }
+    HIP_TRY(hipMemcpyAsync(lv.U, v.U, nb, hipMemcpyDeviceToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(lv.V, v.V, nb, hipMemcpyDeviceToDevice, hs));
+    HIP_TRY(hipMemcpyAsync(lv.D, v.D, nd, hipMemcpyDeviceToDevice, hs));
   }
-  hipError_t e = hipMemcpyAsync(f->D0, D0, sizeof(double) * (size_t)f->n0 * f->n0, hipMemcpyDeviceToDevice, hs);
-  if (e != hipSuccess) {
-    delete f;
-    return from_hip(e);
-  }
-  f->last = hs;
+  HIP_TRY(hipMemcpyAsync(in.D0, D0, sizeof(double) * (size_t)in.n0 * in.n0, hipMemcpyDeviceToDevice, hs));
+  b->last = hs;
+  hbs_factors* f = new (std::nothrow) hbs_factors;
+  if (!f) return HBS_ENOMEM;
+  f->b = b;
+  f->idx = 0;
   *out = f;
   return HBS_OK;
 }
 
 hbs_status hbs_level(const hbs_factors* f, int32_t level, hbs_level_view* out) {
-  if (!f || !out || level < 1 || level > f->L) return HBS_EINVAL;
-  const Level& lv = f->lev[level];
+  if (!f || !out) return HBS_EINVAL;
+  const Instance& in = inst_of(f);
+  if (level < 1 || level > in.L) return HBS_EINVAL;
+  const Level& lv = in.lev[level];
   out->level = level;
   out->nodes = lv.nodes;
   out->m = lv.mmax;
-  out->k = f->k;
+  out->k = in.k;
   out->m_tau = lv.mtau;
   out->U = lv.U;
   out->V = lv.V;
@@ -540,34 +737,37 @@ hbs_status hbs_level(const hbs_factors* f, int32_t level, hbs_level_view* out) {
 
 hbs_status hbs_root(const hbs_factors* f, const double** D0, int32_t* rows) {
   if (!f || !D0 || !rows) return HBS_EINVAL;
-  *D0 = f->D0;
-  *rows = f->n0;
+  const Instance& in = inst_of(f);
+  *D0 = in.D0;
+  *rows = in.n0;
   return HBS_OK;
 }
 
 hbs_status hbs_check(hbs_factors* f) {
   if (!f) return HBS_EINVAL;
-  HIP_TRY(hipStreamSynchronize(f->last));
+  BatchImpl* b = f->b.get();
+  HIP_TRY(hipStreamSynchronize(b->last));
   int32_t flag = 0;
-  HIP_TRY(hipMemcpy(&flag, f->flag, sizeof(int32_t), hipMemcpyDeviceToHost));
-  if (flag) HIP_TRY(hipMemset(f->flag, 0, sizeof(int32_t)));
+  HIP_TRY(hipMemcpy(&flag, b->flag, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (flag) HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));
   return flag ? HBS_ENUMERIC : HBS_OK;
 }
 
 hbs_status hbs_profile(hbs_factors* f, int enable) {
   if (!f) return HBS_EINVAL;
-  f->prof = enable != 0;
+  f->b->prof = enable != 0;
   return HBS_OK;
 }
 
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass) {
-  if (!f || !ms || !launches || nclass < 1 || nclass > 4) return HBS_EINVAL;
+  if (!f || !ms || !launches || nclass < 1 || nclass > 5) return HBS_EINVAL;
+  BatchImpl* b = f->b.get();
   for (int c = 0; c < nclass; ++c) {
     ms[c] = 0.0;
     launches[c] = 0;
   }
-  for (size_t i = 0; i < f->nmarks; ++i) {
-    const auto& m = f->marks[i];
+  for (size_t i = 0; i < b->nmarks; ++i) {
+    const Mark& m = b->marks[i];
     HIP_TRY(hipEventSynchronize(m.b));
     float t = 0.f;
     HIP_TRY(hipEventElapsedTime(&t, m.a, m.b));
@@ -576,7 +776,7 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
       launches[m.cls] += 1;
     }
   }
-  f->nmarks = 0;
+  b->nmarks = 0;
   return HBS_OK;
 }
 

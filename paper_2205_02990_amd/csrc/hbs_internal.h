@@ -9,56 +9,45 @@
 
 namespace hbs {
 
-// Per-level kernel arguments of the side kernel (QR of Omega_tau^*, nullspace
-// sketch, pseudo-inverse solve, truncated QR of the sketch).
-struct SideArgs {
-  const double* Om;   // panel bases; row i of box b is at base + (row0[b] + i) * ld
-  const double* Y;
-  const double* Ps;
-  const double* Z;
-  int64_t ld;
-  const int64_t* row0;  // device [nodes]
-  const int32_t* mtau;  // device [nodes]
-  int32_t nodes, s, k, mmax, mmin;
-  double* U;  // [nodes][mmax][k]   (side 0 writes U, side 1 writes V)
-  double* V;
-  double* W;  // [nodes][mmax][mmax] Y_tau Omega_tau^dagger (side 0) / Z Psi^dagger (side 1)
-  double* X;
-  double* Bt;  // [nodes][2][s][mmax] transposed sketches (Y P)^*, (Z Q)^*
-  int32_t* flag;
-  int32_t root;  // 1: only W = Y Omega^dagger of the single box (written to W)
-};
-
-// Combine: D_tau from U, V, W, X (eq. d_tau_formula).
-struct CombineArgs {
-  const int32_t* mtau;
-  int32_t nodes, k, mmax;
-  const double* U;
-  const double* V;
-  const double* W;
-  const double* X;
-  double* D;     // [nodes][mmax][mmax]
-  double* T;     // workspace [nodes][mmax * mmax + 3 * mmax * k]
-};
-
-// Parent samples: the four k x s blocks of eq. omega_tau_and_y_tau.
-struct ParentArgs {
+// Where a box's test and sample panels live: the caller's inputs of one
+// instance, or the library's reduced panels of one level.  Row i of a box is
+// at base + (row0 + i) * ld.
+struct PanelSrc {
   const double* Om;
   const double* Y;
   const double* Ps;
   const double* Z;
   int64_t ld;
-  const int64_t* row0;
-  const int32_t* mtau;
-  int32_t nodes, s, k, mmax;
-  const double* U;
-  const double* V;
-  const double* D;
-  double* R;         // workspace [nodes][2][mmax][s]
-  double* nOm;       // next level panels, ld = s, box t writes rows [k t, k t + k)
+};
+
+// One box of one sweep launch.  Every launch covers the boxes of one aligned
+// level of one or more instances that share (k, s).
+struct BoxDesc {
+  int64_t row0;   // first panel row of the box in its source
+  int32_t src;    // index into the panel source table
+  int32_t m;      // rows of the box (m_tau)
+  int32_t dld;    // row stride of this box's D, W, X and sketch blocks (>= m)
+  int32_t pad;
+  double* U;      // basis outputs, m x k, row stride k
+  double* V;
+  double* D;      // m x m, stride dld
+  double* W;      // workspace: Y Omega^dagger, m x m, stride dld
+  double* X;      //            Z Psi^dagger
+  double* Bt;     // workspace: [2][s][dld] transposed sketches
+  double* T;      // workspace of the D kernel, dld * dld + 3 * dld * k
+  double* R;      // workspace of the parent kernel, [2][m][s]
+  double* nOm;    // parent panels: k rows each, ld = s (null at the root)
   double* nY;
   double* nPs;
   double* nZ;
+};
+
+struct SweepArgs {
+  const BoxDesc* box;
+  const PanelSrc* src;
+  int32_t nboxes, k, s, mmax, mmin;
+  int32_t root;   // 1: only W = Y Omega^dagger of each box (written to D)
+  int32_t* flag;
 };
 
 // Apply: one level of the upward or downward pass of Algorithm 1.
@@ -80,9 +69,14 @@ struct ApplyArgs {
 };
 
 bool side_supported(int mmin, int mmax, int s, int k, bool root);
-hipError_t launch_side(const SideArgs& a, hipStream_t st);
-hipError_t launch_combine(const CombineArgs& a, hipStream_t st);
-hipError_t launch_parent(const ParentArgs& a, hipStream_t st);
+hipError_t prepare_side_kernels();
+// QR of the test blocks, reflectors applied to the samples, Y Omega^dagger
+// (both sides of every box; the root's one side)
+hipError_t launch_lq(const SweepArgs& a, hipStream_t st);
+// truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
+hipError_t launch_col(const SweepArgs& a, hipStream_t st);
+hipError_t launch_combine(const SweepArgs& a, hipStream_t st);
+hipError_t launch_parent(const SweepArgs& a, hipStream_t st);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_dense_small(const double* A, int64_t lda, int32_t transA, const double* Bm, int64_t ldb,

@@ -63,6 +63,15 @@ def load():
         "hbs_sample_logkernel": (I32, [I64, VP, VP, VP, VP, VP, VP, I32, I64, I32, VP]),
         "hbs_profile": (I32, [P, ctypes.c_int]),
         "hbs_profile_read": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32]),
+        "hbs_batch_create": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(I32), I32,
+                                   ctypes.POINTER(P)]),
+        "hbs_batch_destroy": (None, [P]),
+        "hbs_batch_compress": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                     ctypes.POINTER(P), ctypes.POINTER(I64), VP]),
+        "hbs_batch_factors": (I32, [P, I32, ctypes.POINTER(P)]),
+        "hbs_compress_batched": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(I32),
+                                       ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
+                                       ctypes.POINTER(P), ctypes.POINTER(I64), I32, VP, ctypes.POINTER(P)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -191,11 +200,7 @@ class Factors:
 
     def profile_read(self) -> dict:
         """Summed device ms and launch counts per kernel class since the last read."""
-        ms = (ctypes.c_double * 4)()
-        n = (ctypes.c_int64 * 4)()
-        _check(load().hbs_profile_read(self._h, ms, n, 4), "hbs_profile_read")
-        names = ("side", "combine", "parent", "root")
-        return {names[i]: (ms[i], n[i]) for i in range(4)}
+        return _profile_read(self._h)
 
     def level(self, level: int, stream=None) -> dict:
         v = LevelView()
@@ -214,6 +219,87 @@ class Factors:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.hbs_factors_destroy(self._h)
             self._h = None
+
+
+PROFILE_CLASSES = ("lq", "col", "combine", "parent", "root")
+
+
+def _profile_read(h) -> dict:
+    nc = len(PROFILE_CLASSES)
+    ms = (ctypes.c_double * nc)()
+    n = (ctypes.c_int64 * nc)()
+    _check(load().hbs_profile_read(h, ms, n, nc), "hbs_profile_read")
+    return {PROFILE_CLASSES[i]: (ms[i], n[i]) for i in range(nc)}
+
+
+def _ptrs(ts, name):
+    return (ctypes.c_void_p * len(ts))(*[_dev_f64(t, f"{name}[{i}]").value for i, t in enumerate(ts)])
+
+
+class Batch:
+    """Independent compressions sharing one sweep (hbs_batch_*)."""
+
+    def __init__(self, trees, ks, ss, precision: str = "fp64"):
+        lib = load()
+        c = len(trees)
+        self.trees = list(trees)
+        self.ks = [int(x) for x in ks]
+        self.ss = [int(x) for x in ss]
+        th = (ctypes.c_void_p * c)(*[t._h.value for t in self.trees])
+        h = ctypes.c_void_p()
+        _check(lib.hbs_batch_create(c, th, (ctypes.c_int32 * c)(*self.ks), (ctypes.c_int32 * c)(*self.ss),
+                                    PRECISION[precision], ctypes.byref(h)), "hbs_batch_create")
+        self._h = h
+
+    def __len__(self):
+        return len(self.trees)
+
+    def compress(self, Om, Y, Ps, Z, stream=None):
+        """Om, Y, Ps, Z: lists of per-instance N_i x s_i device tensors."""
+        c = len(self.trees)
+        if not all(len(x) == c for x in (Om, Y, Ps, Z)):
+            raise ValueError("one panel of each kind per instance")
+        ld = []
+        for i in range(c):
+            l0 = Om[i].stride(0)
+            if any(t.stride(0) != l0 for t in (Y[i], Ps[i], Z[i])):
+                raise ValueError("the panels of one instance must share a leading dimension")
+            ld.append(l0)
+        _check(load().hbs_batch_compress(self._h, _ptrs(Om, "Omega"), _ptrs(Y, "Y"), _ptrs(Ps, "Psi"),
+                                         _ptrs(Z, "Z"), (ctypes.c_int64 * c)(*ld), _stream(stream)),
+               "hbs_batch_compress")
+        return self
+
+    def factors(self, i: int) -> Factors:
+        h = ctypes.c_void_p()
+        _check(load().hbs_batch_factors(self._h, int(i), ctypes.byref(h)), "hbs_batch_factors")
+        f = Factors(h, self.trees[i], self.ks[i])
+        f.s = self.ss[i]
+        return f
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbs_batch_destroy(self._h)
+            self._h = None
+
+
+def compress_batched(trees, ks, Om, Y, Ps, Z, precision: str = "fp64", stream=None):
+    """hbs_compress_batched: one Factors per instance."""
+    c = len(trees)
+    ld = [t.stride(0) for t in Om]
+    th = (ctypes.c_void_p * c)(*[t._h.value for t in trees])
+    ss = [t.shape[1] for t in Om]
+    out = (ctypes.c_void_p * c)()
+    _check(load().hbs_compress_batched(c, th, (ctypes.c_int32 * c)(*[int(k) for k in ks]),
+                                       (ctypes.c_int32 * c)(*ss), _ptrs(Om, "Omega"), _ptrs(Y, "Y"),
+                                       _ptrs(Ps, "Psi"), _ptrs(Z, "Z"), (ctypes.c_int64 * c)(*ld),
+                                       PRECISION[precision], _stream(stream), out), "hbs_compress_batched")
+    res = []
+    for i in range(c):
+        f = Factors(ctypes.c_void_p(out[i]), trees[i], ks[i])
+        f.s = ss[i]
+        res.append(f)
+    return res
 
 
 def compress(tree: Tree, k: int, Om, Y, Ps, Z, precision: str = "fp64", stream=None) -> Factors:
