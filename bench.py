@@ -50,36 +50,31 @@ def col_flops(m, s, k):
     return 4 * m * r * k - 2 * (m + r) * k * k + 4 * k ** 3 / 3 + 2 * m * k * k - 2 * k ** 3 / 3
 
 
-def combine_flops(m, k):
-    """D_tau: five m x m x k products."""
-    return 10 * m * m * k
-
-
-def parent_flops(m, s, k):
-    """V^* Omega, U^* Psi (2 m k s each) and U^*(Y - D Omega), V^*(Z - D^* Psi)
-    (2 m^2 s + 2 m k s each)."""
-    return 4 * m * k * s + 2 * (2 * m * m * s + 2 * m * k * s)
+def tail_flops(m, s, k):
+    """The products after the bases: X U, W V, U^* W, and U times the k x m
+    term of D (2 m^2 k each); V^* F, U^* Q, V G, U G2 (2 m k^2 each); and the
+    six k x m x s products with the test and sample blocks (2 k m s each)."""
+    return 8 * m * m * k + 8 * m * k * k + 12 * k * m * s
 
 
 def sweep_model(leaf_sizes, k, s):
     """Per-step flop totals by kernel class, algorithmic HBM bytes of the QR
     kernel, and the launch count of each per-level kernel."""
     L = int(round(math.log2(len(leaf_sizes))))
-    lq = col = comb = par = 0.0
+    lq = col = tail = 0.0
     lq_bytes = 0
     for lev in range(L, 0, -1):
         ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
         for m in ms:
             lq += 2 * lq_flops(m, s)
             col += 2 * col_flops(m, s, k)
-            comb += combine_flops(m, k)
-            par += parent_flops(m, s, k)
+            tail += tail_flops(m, s, k)
             # each side reads its two m x s panels, writes W (m x m) and the
             # transposed m x (s - m) nullspace sketch
             lq_bytes += 2 * 8 * (2 * m * s + m * m + m * (s - m))
     m0 = 2 * k if L > 0 else leaf_sizes[0]
     root = lq_flops(m0, s)
-    return {"lq": lq, "col": col, "combine": comb, "parent": par, "root": root, "launches": L,
+    return {"lq": lq, "col": col, "tail": tail, "root": root, "launches": L,
             "lq_bytes": lq_bytes}
 
 
@@ -123,7 +118,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="logkernel_ellipse_n65536_k50")
-    ap.add_argument("--path", default="fp64", choices=["fp64"])
+    ap.add_argument("--path", default="fp64", choices=["fp64", "split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subtree-level", type=int, default=4)
     args = ap.parse_args()
@@ -228,7 +223,7 @@ def main():
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "kernel": "lq_kernel", "flops_per_launch": per_launch, "avg_launch_ms": avg_launch_ms,
                 "algorithmic_hbm_bytes_per_launch": model["lq_bytes"] / model["launches"]}
-    total_flops = sum(model[c] for c in ("lq", "col", "combine", "parent", "root"))
+    total_flops = sum(model[c] for c in ("lq", "col", "tail", "root"))
 
     out = {
         "metric": METRIC, "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,

@@ -45,7 +45,11 @@ typedef enum {
 
 typedef enum {
   HBS_FP64 = 0,           /* every product in FP64                              */
-  HBS_FP32_SPLIT = 1,     /* bulk products on MFMA from exact BF16 slices       */
+  HBS_FP32_SPLIT = 1,     /* split precision: every product with a test or
+                           * sample block from exact 7-bit integer slices on
+                           * the int8 matrix cores, recombined in FP64 (about
+                           * 1e-14 relative per product); QR, bases, solves
+                           * and D_tau stay FP64                               */
   HBS_BF16 = 2            /* log-kernel sampler only: BF16 operands, FP32 sums  */
 } hbs_precision;
 
@@ -177,12 +181,14 @@ const char* hbs_status_str(hbs_status s);
  *     solve for Y_tau Omega_tau^dagger (sections 2.4, 4.1)
  *   1 truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
  *     (section 2.2, eqs. u_tau_formula, v_tau_formula)
- *   2 discrepancy block D_tau (eq. d_tau_formula)
- *   3 reduced samples for the parent level (eq. omega_tau_and_y_tau)
- *   4 root block D^(0) */
+ *   2 products of the bases with W, X and with the test and sample blocks
+ *   3 the small k-wide terms of D_tau (eq. d_tau_formula)
+ *   4 D_tau and the corrections of the parent blocks (eq.
+ *     omega_tau_and_y_tau)
+ *   5 root block D^(0) */
 hbs_status hbs_profile(hbs_factors* f, int enable);
 /* Wait for the recorded work, then write the summed device time in ms and
- * the launch count of each class (arrays of nclass <= 5 entries, host
+ * the launch count of each class (arrays of nclass <= 6 entries, host
  * memory) accumulated since the previous read, and reset them. */
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass);
 

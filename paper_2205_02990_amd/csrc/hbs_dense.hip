@@ -1,5 +1,5 @@
-// Batched small products of the sweep and of the apply: one workgroup per box
-// (and per output block), operands staged through LDS, FP64 register tiles.
+// Batched small products of the apply (Algorithm 1): one workgroup per box,
+// operands staged through LDS, FP64 register tiles.
 #include "hbs_internal.h"
 
 namespace hbs {
@@ -104,71 +104,6 @@ __device__ void tile_gemm(int M, int N, int K, double alpha, const double* __res
   __syncthreads();
 }
 
-// D_tau of eq. d_tau_formula, evaluated as
-//   F = X U,  G = V^* F,  E = F - V G = (I - V V^*) X U,
-//   T = U^* W - E^*,  D = W - U T = (I - U U^*) W + U U^* ((I - V V^*) X)^*.
-template <int TK>
-__global__ void __launch_bounds__(kNT) combine_kernel(SweepArgs a) {
-  __shared__ GemmSmem<TK> sm;
-  const BoxDesc& bx = a.box[blockIdx.x];
-  const int m = bx.m, k = a.k, mm = bx.dld;
-  const double* U = bx.U;
-  const double* V = bx.V;
-  const double* W = bx.W;
-  const double* X = bx.X;
-  double* D = bx.D;
-  double* F = bx.T;                                         // m x k
-  double* Gm = F + mm * k;                                  // k x k
-  double* E = Gm + mm * k;                                  // m x k
-  double* T = E + mm * k;                                   // k x m
-  tile_gemm(m, k, m, 1.0, X, mm, 1, U, k, 1, 0.0, nullptr, 0, F, k, sm);       // F = X U
-  tile_gemm(k, k, m, 1.0, V, 1, k, F, k, 1, 0.0, nullptr, 0, Gm, k, sm);      // G = V^* F
-  tile_gemm(m, k, k, -1.0, V, k, 1, Gm, k, 1, 1.0, F, k, E, k, sm);           // E = F - V G
-  tile_gemm(k, m, m, 1.0, U, 1, k, W, mm, 1, 0.0, nullptr, 0, T, m, sm);      // T = U^* W
-  for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {
-    const int i = idx / m, j = idx % m;
-    T[i * m + j] -= E[j * k + i];                                            // T -= E^*
-  }
-  __syncthreads();
-  tile_gemm(m, m, k, -1.0, U, k, 1, T, m, 1, 1.0, W, mm, D, mm, sm);          // D = W - U T
-}
-
-// The four k x s blocks one child hands to its parent (eq.
-// omega_tau_and_y_tau; Psi and Z rows as in Algorithm 2):
-//   y = 0: V^* Omega_tau      y = 1: U^* (Y_tau - D_tau Omega_tau)
-//   y = 2: U^* Psi_tau        y = 3: V^* (Z_tau - D_tau^* Psi_tau)
-// Child t writes rows [k t, k t + k) of the next level's panels (ld = s).
-template <int TK>
-__global__ void __launch_bounds__(kNT) parent_kernel(SweepArgs a) {
-  __shared__ GemmSmem<TK> sm;
-  const BoxDesc& bx = a.box[blockIdx.x];
-  const PanelSrc& ps = a.src[bx.src];
-  const int which = blockIdx.y;
-  const int c0 = blockIdx.z * TN;
-  const int m = bx.m, k = a.k, s = a.s, mm = bx.dld;
-  const int nc = (s - c0) < TN ? (s - c0) : TN;
-  const int64_t ld = ps.ld;
-  const int64_t r0 = bx.row0;
-  const double* U = bx.U;
-  const double* V = bx.V;
-  const double* D = bx.D;
-  const double* Bas = (which == 0 || which == 3) ? V : U;
-  const double* Tst = ((which < 2) ? ps.Om : ps.Ps) + r0 * ld + c0;
-  double* out = ((which == 0) ? bx.nOm : (which == 1) ? bx.nY : (which == 2) ? bx.nPs : bx.nZ) + c0;
-  if (which == 0 || which == 2) {
-    tile_gemm(k, nc, m, 1.0, Bas, 1, k, Tst, ld, 1, 0.0, nullptr, 0, out, s, sm);
-    return;
-  }
-  const double* Smp = ((which == 1) ? ps.Y : ps.Z) + r0 * ld + c0;
-  double* R = bx.R + (int64_t)(which == 3) * m * s + c0;
-  // R = Smp - D Tst  (D^* for the Z side)
-  if (which == 1)
-    tile_gemm(m, nc, m, -1.0, D, mm, 1, Tst, ld, 1, 1.0, Smp, ld, R, s, sm);
-  else
-    tile_gemm(m, nc, m, -1.0, D, 1, mm, Tst, ld, 1, 1.0, Smp, ld, R, s, sm);
-  tile_gemm(k, nc, m, 1.0, Bas, 1, k, R, s, 1, 0.0, nullptr, 0, out, s, sm);
-}
-
 // Upward pass of Algorithm 1 on one level: qhat_tau = B_tau^* in_tau, where
 // in_tau is q(I_tau, :) at the leaves and [qhat_alpha; qhat_beta] above.
 __global__ void __launch_bounds__(kNT) apply_up_kernel(ApplyArgs a) {
@@ -218,24 +153,6 @@ __global__ void __launch_bounds__(kNT) dense_small_kernel(const double* A, int64
 }
 
 }  // namespace
-
-// Levels with few boxes are latency bound: deeper K chunks there.
-hipError_t launch_combine(const SweepArgs& a, hipStream_t st) {
-  if (a.nboxes < 256)
-    hipLaunchKernelGGL(combine_kernel<32>, dim3(a.nboxes), dim3(kNT), 0, st, a);
-  else
-    hipLaunchKernelGGL(combine_kernel<16>, dim3(a.nboxes), dim3(kNT), 0, st, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_parent(const SweepArgs& a, hipStream_t st) {
-  const dim3 grid(a.nboxes, 4, (a.s + TN - 1) / TN);
-  if (a.nboxes < 256)
-    hipLaunchKernelGGL(parent_kernel<32>, grid, dim3(kNT), 0, st, a);
-  else
-    hipLaunchKernelGGL(parent_kernel<16>, grid, dim3(kNT), 0, st, a);
-  return hipGetLastError();
-}
 
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st) {
   hipLaunchKernelGGL(apply_up_kernel, dim3(a.nodes), dim3(kNT), 0, st, a);

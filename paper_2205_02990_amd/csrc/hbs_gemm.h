@@ -1,0 +1,280 @@
+// Workgroup-level products on the matrix cores of gfx950, called by every
+// thread of a workgroup:
+//   mfma_gemm  FP64 products on v_mfma_f64_16x16x4f64;
+//   sliced_lt  the split-precision product L^T R: both operands cut into
+//              exact 7-bit integer slices (one power-of-two scale per row of
+//              L^T and per column of R), the slice pairs multiplied exactly on
+//              v_mfma_i32_16x16x64_i8 with 32-bit integer sums, recombined in
+//              FP64 (error-free slicing in the manner of Ozaki, Ogita, Oishi
+//              and Rump, with integer slices).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace hbs {
+
+constexpr int kGemmThreads = 256;   // FP64 product workgroups
+constexpr int kSliceThreads = 512;  // split-precision product workgroups
+
+typedef double gemm_d4 __attribute__((ext_vector_type(4)));
+typedef int gemm_i4 __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// FP64: C(i, j) = alpha * sum_kk A(i, kk) B(kk, j) + beta * C0(i, j), i < M,
+// j < N, with A(i, kk) = A[i * sar + kk * sac], B(kk, j) = B[kk * sbr + j * sbc]
+// (strides express transposes).  64 x 64 output tiles; with NT = 256 threads
+// each wave owns a 32 x 32 quarter (2 x 2 MFMA blocks of 16 x 16), with 512 a
+// 16 x 32 eighth (1 x 2 blocks).  K is staged through LDS
+// in chunks of TK with the next chunk's global loads in flight during the
+// products.  C0 may alias C.  Ends with a barrier.
+//
+// Lane layouts of v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, l / 16)
+// and B(l / 16, l % 16) and receives C(l / 16 + 4 r, l % 16) in element r.
+template <int TK>
+struct MfmaSmem {
+  double As[TK][65];  // As[kk][i]
+  double Bs[TK][65];  // Bs[kk][j]
+};
+
+template <int TK, int NT = kGemmThreads>
+__device__ __forceinline__ void mfma_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int64_t sar,
+                          int64_t sac, const double* __restrict__ B, int64_t sbr, int64_t sbc, double beta,
+                          const double* C0, int64_t ldc0, double* C, int64_t ldc, MfmaSmem<TK>& sm) {
+  static_assert(TK % 4 == 0, "K chunk must be a multiple of the MFMA depth");
+  static_assert(NT == 256 || NT == 512, "4 or 8 waves");
+  constexpr int LA = 64 * TK / NT;
+  constexpr int TR = (NT == 256) ? 2 : 1;  // 16-row blocks per wave
+  static_assert(LA >= 1, "chunk too small for the workgroup");
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rb = (wv >> 1) * 16 * TR, cb = (wv & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // staging coordinates: coalesced along whichever index is contiguous
+  int ai[LA], ak[LA], bj[LA], bk[LA];
+#pragma unroll
+  for (int r = 0; r < LA; ++r) {
+    const int idx = tid + r * NT;
+    ai[r] = (sac == 1) ? idx / TK : idx % 64;
+    ak[r] = (sac == 1) ? idx % TK : idx / 64;
+    bj[r] = (sbc == 1) ? idx % 64 : idx / TK;
+    bk[r] = (sbc == 1) ? idx / 64 : idx % TK;
+  }
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      gemm_d4 acc[TR][2];
+#pragma unroll
+      for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = gemm_d4{0.0, 0.0, 0.0, 0.0};
+      double pa[LA], pb[LA];
+      auto fetch = [&](int k0) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+          const int gi = i0 + ai[r], gk = k0 + ak[r];
+          const bool ok = gi < M && gk < K;
+          const double v = A[ok ? gi * sar + gk * sac : 0];
+          pa[r] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < LA; ++r) {
+          const int gj = j0 + bj[r], gk = k0 + bk[r];
+          const bool ok = gj < N && gk < K;
+          const double v = B[ok ? gk * sbr + gj * sbc : 0];
+          pb[r] = ok ? v : 0.0;
+        }
+      };
+      fetch(0);
+      for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+        for (int r = 0; r < LA; ++r) sm.As[ak[r]][ai[r]] = pa[r];
+#pragma unroll
+        for (int r = 0; r < LA; ++r) sm.Bs[bk[r]][bj[r]] = pb[r];
+        __syncthreads();
+        if (k0 + TK < K) fetch(k0 + TK);
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+          const double b0 = sm.Bs[kk + lk][cb + li], b1 = sm.Bs[kk + lk][cb + 16 + li];
+#pragma unroll
+          for (int a = 0; a < TR; ++a) {
+            const double av = sm.As[kk + lk][rb + 16 * a + li];
+            acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[a][0], 0, 0, 0);
+            acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[a][1], 0, 0, 0);
+          }
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int a = 0; a < TR; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int gi = i0 + rb + 16 * a + lk + 4 * r, gj = j0 + cb + 16 * b + li;
+            if (gi < M && gj < N) {
+              const double v = alpha * acc[a][b][r];
+              C[gi * ldc + gj] = (beta != 0.0) ? beta * C0[gi * ldc0 + gj] + v : v;
+            }
+          }
+    }
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------------------
+// Split precision: C(i, j) = alpha * sum_kk L(kk, i) R(kk, j) + beta * C0(i, j)
+// for i < M, j < N, kk < K, with L(kk, i) = L[kk * ldl + i] and
+// R(kk, j) = R[kk * ldr + j] (row-major, the output index contiguous).
+//
+// Row i of L^T is scaled by 2^-e_i with e_i the binary exponent of its
+// largest magnitude (so every scaled entry lies in (-1, 1)), column j of R by
+// 2^-f_j likewise.  A scaled entry t is cut into S integer slices
+// q_p = trunc(128 t_p), t_{p+1} = 128 t_p - q_p (t_1 = t), so that
+// t = sum_p q_p 2^(-7p) + a remainder below 2^(-7S); each q_p lies in
+// [-127, 127].  Products of slice pairs (p, q) with p + q <= S + 1 are exact
+// in 32-bit integer sums (at most S pairs per diagonal: |sum| <= S K 127^2,
+// below 2^31 for K < 2^31 / (S 127^2), 19000 at S = 7) and
+// are accumulated per diagonal p + q; the diagonals are combined in FP64:
+//   C(i, j) ~ 2^(e_i + f_j) sum_d 2^(-7 d) acc_d(i, j).
+// Dropped pairs and slice remainders bound the error of each entry by about
+// (S + 3) K 2^(-7S) max|L(., i)| max|R(., j)|.
+//
+// Lane layouts of v_mfma_i32_16x16x64_i8: lane l supplies 16 bytes of row
+// l % 16 of the left operand and of column l % 16 of the right operand, for
+// the same 16 values of the contracted index (l / 16 selects which 16); it
+// receives C(4 (l / 16) + r, l % 16) in element r.  Called by the 512
+// threads of a workgroup; each of its 8 waves owns a 16 x 32 strip of each
+// 64 x 64 output tile.
+constexpr int kSliceK = 64;                 // contracted indices per LDS chunk
+constexpr int kSliceRow = kSliceK / 4 + 4;  // int32 words per slice row (16 bytes of padding)
+constexpr int kSliceGroups = kSliceThreads / 64;     // contracted-index groups in staging
+constexpr int kSlicePer = kSliceK / kSliceGroups;    // contracted indices per staging thread
+
+template <int S>
+struct SliceSmem {
+  int32_t As[S][64][kSliceRow];  // As[p][i][kk / 4]: four slices q_p of L(kk, i) per word
+  int32_t Bs[S][64][kSliceRow];
+  double red[2][kSliceGroups][64];  // partial maxima
+  int ea[64], eb[64];               // scale exponents
+};
+
+// Cut 4 values (scaled by 2^-e) into S slices, one word of packed bytes each.
+template <int S>
+__device__ __forceinline__ void slice4(const double (&x)[4], int e, int32_t (&w)[S]) {
+#pragma unroll
+  for (int p = 0; p < S; ++p) w[p] = 0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double t = ldexp(x[c], -e);
+#pragma unroll
+    for (int p = 0; p < S; ++p) {
+      const double v = t * 128.0;
+      const double q = trunc(v);
+      t = v - q;
+      w[p] |= ((int32_t)q & 0xff) << (8 * c);
+    }
+  }
+}
+
+// Slice contracted indices [k0 + kSlicePer g, k0 + kSlicePer (g + 1)) of column
+// c0 + c of a row-major operand X (K x ncol, row stride ldx) into
+// dst[p][c][words of those indices].
+template <int S>
+__device__ __forceinline__ void slice_stage(const double* __restrict__ X, int64_t ldx, int c0, int ncol, int K, int k0, int c,
+                                   int g, int e, int32_t (*dst)[64][kSliceRow]) {
+  const bool okc = c0 + c < ncol;
+#pragma unroll
+  for (int w = 0; w < kSlicePer / 4; ++w) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + kSlicePer * g + 4 * w + u;
+      const bool ok = okc && kk < K;
+      const double v = X[ok ? kk * ldx + c0 + c : 0];
+      x[u] = ok ? v : 0.0;
+    }
+    int32_t sw[S];
+    slice4<S>(x, e, sw);
+#pragma unroll
+    for (int p = 0; p < S; ++p) dst[p][c][(kSlicePer / 4) * g + w] = sw[p];
+  }
+}
+
+template <int S>
+__device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, const double* __restrict__ L, int64_t ldl,
+                          const double* __restrict__ R, int64_t ldr, double beta, const double* C0, int64_t ldc0,
+                          double* C, int64_t ldc, SliceSmem<S>& sm) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rb = (wv >> 1) * 16, cb = (wv & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  const int c = tid & 63, g = tid >> 6;  // staging: output index c, contracted group g
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      // scales: largest magnitude of each row of L^T and each column of R
+      {
+        const bool oki = i0 + c < M, okj = j0 + c < N;
+        double ma = 0.0, mb = 0.0;
+        for (int kk = g; kk < K; kk += kSliceGroups) {
+          const double va = L[oki ? kk * ldl + i0 + c : 0];
+          const double vb = R[okj ? kk * ldr + j0 + c : 0];
+          ma = fmax(ma, oki ? fabs(va) : 0.0);
+          mb = fmax(mb, okj ? fabs(vb) : 0.0);
+        }
+        sm.red[0][g][c] = ma;
+        sm.red[1][g][c] = mb;
+        __syncthreads();
+        if (tid < 128) {
+          const int h = tid >> 6;
+          double mx = 0.0;
+#pragma unroll
+          for (int q = 0; q < kSliceGroups; ++q) mx = fmax(mx, sm.red[h][q][c]);
+          int e = 0;
+          (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1); 0 for mx = 0
+          (h ? sm.eb : sm.ea)[c] = e;
+        }
+        __syncthreads();
+      }
+      gemm_i4 acc[2][S];
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int d = 0; d < S; ++d) acc[b][d] = gemm_i4{0, 0, 0, 0};
+      for (int k0 = 0; k0 < K; k0 += kSliceK) {
+        slice_stage<S>(L, ldl, i0, M, K, k0, c, g, sm.ea[c], sm.As);
+        slice_stage<S>(R, ldr, j0, N, K, k0, c, g, sm.eb[c], sm.Bs);
+        __syncthreads();
+        gemm_i4 ap[S];
+#pragma unroll
+        for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.As[p][rb + li][4 * lk]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          gemm_i4 bq[S];
+#pragma unroll
+          for (int q = 0; q < S; ++q) bq[q] = *reinterpret_cast<const gemm_i4*>(&sm.Bs[q][cb + 16 * b + li][4 * lk]);
+#pragma unroll
+          for (int p = 0; p < S; ++p)
+#pragma unroll
+            for (int q = 0; p + q < S; ++q)
+              acc[b][p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq[q], acc[b][p + q], 0, 0, 0);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ti = rb + 4 * lk + r, tj = cb + 16 * b + li;
+          const int gi = i0 + ti, gj = j0 + tj;
+          if (gi < M && gj < N) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = S - 1; d >= 0; --d) v += ldexp((double)acc[b][d][r], -7 * (d + 2));
+            v = alpha * ldexp(v, sm.ea[ti] + sm.eb[tj]);
+            C[gi * ldc + gj] = (beta != 0.0) ? beta * C0[gi * ldc0 + gj] + v : v;
+          }
+        }
+      __syncthreads();
+    }
+  }
+}
+
+}  // namespace hbs

@@ -79,6 +79,7 @@ struct Mark {
 // (k, s) class covers the boxes of all of them.
 struct BatchImpl {
   std::vector<Instance> inst;
+  hbs_precision prec = HBS_FP64;
   std::vector<void*> allocs;
   hbs::PanelSrc* h_src = nullptr;  // pinned host copy of the panel-source table
   hbs::PanelSrc* d_src = nullptr;
@@ -245,7 +246,7 @@ hbs_status build_sweep(BatchImpl* b) {
   std::memset(b->h_src, 0, sizeof(hbs::PanelSrc) * nsrc);
   for (Instance& in : b->inst)
     for (int l = 0; l < in.L; ++l)
-      b->h_src[in.src_lev[l]] = hbs::PanelSrc{in.lev[l].bOm, in.lev[l].bY, in.lev[l].bPs, in.lev[l].bZ, in.s};
+      b->h_src[in.src_lev[l]] = hbs::PanelSrc{{in.lev[l].bOm, in.lev[l].bY, in.lev[l].bPs, in.lev[l].bZ}, in.s};
   HIP_TRY(b->alloc((void**)&b->d_src, sizeof(hbs::PanelSrc) * nsrc));
 
   int maxL = 0;
@@ -284,13 +285,13 @@ hbs_status build_sweep(BatchImpl* b) {
         d.U = lv.U + (size_t)i * lv.mmax * k;
         d.V = lv.V + (size_t)i * lv.mmax * k;
         d.D = lv.D + (size_t)i * lv.mmax * lv.mmax;
-        d.nOm = up.bOm + (size_t)k * i * s;
-        d.nY = up.bY + (size_t)k * i * s;
-        d.nPs = up.bPs + (size_t)k * i * s;
-        d.nZ = up.bZ + (size_t)k * i * s;
+        d.np[hbs::kOm] = up.bOm + (size_t)k * i * s;
+        d.np[hbs::kY] = up.bY + (size_t)k * i * s;
+        d.np[hbs::kPs] = up.bPs + (size_t)k * i * s;
+        d.np[hbs::kZ] = up.bZ + (size_t)k * i * s;
         const size_t dl = lv.mmax;
         g.boxes.push_back(d);
-        g.ws.push_back(3 * dl * dl + 3 * dl * k + 4 * dl * s);
+        g.ws.push_back(2 * dl * dl + 2 * dl * s + hbs::tail_workspace((int)dl, k));
       }
     }
     hbs::BoxDesc d{};
@@ -329,9 +330,8 @@ hbs_status build_sweep(BatchImpl* b) {
           const size_t dl = d.dld, kk = g.k, ss = g.s;
           d.W = ws + off;
           d.X = d.W + dl * dl;
-          d.T = d.X + dl * dl;
-          d.Bt = d.T + dl * dl + 3 * dl * kk;
-          d.R = d.Bt + 2 * ss * dl;
+          d.Bt = d.X + dl * dl;
+          d.T = d.Bt + 2 * ss * dl;
           off += g.ws[q];
         }
         mmax = std::max(mmax, d.m);
@@ -347,6 +347,7 @@ hbs_status build_sweep(BatchImpl* b) {
       ln.args.mmax = mmax;
       ln.args.mmin = mmin;
       ln.args.root = g.root ? 1 : 0;
+      ln.args.mixed = b->prec == HBS_FP32_SPLIT ? 1 : 0;
       ln.args.flag = b->flag;
       b->launches.push_back(ln);
     }
@@ -358,19 +359,18 @@ hbs_status build_sweep(BatchImpl* b) {
 
 hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
   for (const Launch& ln : b->launches) {
-    HIP_TRY(b->mark_begin(ln.args.root ? 4 : 0, st));
+    HIP_TRY(b->mark_begin(ln.args.root ? 5 : 0, st));
     HIP_TRY(hbs::launch_lq(ln.args, st));
     HIP_TRY(b->mark_end(st));
     if (ln.args.root) continue;
     HIP_TRY(b->mark_begin(1, st));
     HIP_TRY(hbs::launch_col(ln.args, st));
     HIP_TRY(b->mark_end(st));
-    HIP_TRY(b->mark_begin(2, st));
-    HIP_TRY(hbs::launch_combine(ln.args, st));
-    HIP_TRY(b->mark_end(st));
-    HIP_TRY(b->mark_begin(3, st));
-    HIP_TRY(hbs::launch_parent(ln.args, st));
-    HIP_TRY(b->mark_end(st));
+    for (int part = 0; part < 3; ++part) {
+      HIP_TRY(b->mark_begin(2 + part, st));
+      HIP_TRY(hbs::launch_tail(ln.args, part, st));
+      HIP_TRY(b->mark_end(st));
+    }
   }
   return HBS_OK;
 }
@@ -405,7 +405,7 @@ hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
 hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
                       hbs_precision prec, bool with_sweep, std::shared_ptr<BatchImpl>* out) {
   if (count < 1 || !trees || !k || (with_sweep && !s)) return HBS_EINVAL;
-  if (prec != HBS_FP64) return HBS_EUNSUPPORTED;
+  if (prec != HBS_FP64 && prec != HBS_FP32_SPLIT) return HBS_EUNSUPPORTED;
   for (int i = 0; i < count; ++i) {
     if (with_sweep) {
       hbs_status st = check_shape(trees[i], k[i], s[i]);
@@ -416,6 +416,7 @@ hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t
   }
   std::shared_ptr<BatchImpl> b(new (std::nothrow) BatchImpl);
   if (!b) return HBS_ENOMEM;
+  b->prec = prec;
   HIP_TRY(b->alloc((void**)&b->flag, sizeof(int32_t)));
   HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));
   b->inst.resize(count);
@@ -527,7 +528,7 @@ hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* 
   if (!b->sweep_ready || b->inst.size() != 1) return HBS_EINVAL;  // imported sets, batch members
   Instance& in = b->inst[0];
   if (ld < in.s) return HBS_EINVAL;
-  b->h_src[in.src_in] = hbs::PanelSrc{Omega, Y, Psi, Z, ld};
+  b->h_src[in.src_in] = hbs::PanelSrc{{Omega, Y, Psi, Z}, ld};
   return run_sweep(b, (hipStream_t)hip_stream);
 }
 
@@ -575,7 +576,7 @@ hbs_status hbs_batch_compress(hbs_batch* h, const double* const* Omega, const do
     if (!Omega[i] || !Y[i] || !Psi[i] || !Z[i] || ld[i] < in.s) return HBS_EINVAL;
   }
   for (size_t i = 0; i < b->inst.size(); ++i)
-    b->h_src[b->inst[i].src_in] = hbs::PanelSrc{Omega[i], Y[i], Psi[i], Z[i], ld[i]};
+    b->h_src[b->inst[i].src_in] = hbs::PanelSrc{{Omega[i], Y[i], Psi[i], Z[i]}, ld[i]};
   return run_sweep(b, (hipStream_t)hip_stream);
 }
 
@@ -760,7 +761,7 @@ hbs_status hbs_profile(hbs_factors* f, int enable) {
 }
 
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass) {
-  if (!f || !ms || !launches || nclass < 1 || nclass > 5) return HBS_EINVAL;
+  if (!f || !ms || !launches || nclass < 1 || nclass > 6) return HBS_EINVAL;
   BatchImpl* b = f->b.get();
   for (int c = 0; c < nclass; ++c) {
     ms[c] = 0.0;

@@ -12,11 +12,9 @@ namespace hbs {
 // Where a box's test and sample panels live: the caller's inputs of one
 // instance, or the library's reduced panels of one level.  Row i of a box is
 // at base + (row0 + i) * ld.
+enum PanelKind { kOm = 0, kY = 1, kPs = 2, kZ = 3 };
 struct PanelSrc {
-  const double* Om;
-  const double* Y;
-  const double* Ps;
-  const double* Z;
+  const double* p[4];  // Omega, Y, Psi, Z (indexed by PanelKind)
   int64_t ld;
 };
 
@@ -34,12 +32,8 @@ struct BoxDesc {
   double* W;      // workspace: Y Omega^dagger, m x m, stride dld
   double* X;      //            Z Psi^dagger
   double* Bt;     // workspace: [2][s][dld] transposed sketches
-  double* T;      // workspace of the D kernel, dld * dld + 3 * dld * k
-  double* R;      // workspace of the parent kernel, [2][m][s]
-  double* nOm;    // parent panels: k rows each, ld = s (null at the root)
-  double* nY;
-  double* nPs;
-  double* nZ;
+  double* T;      // workspace of the tail kernels, tail_workspace(dld, k) doubles
+  double* np[4];  // parent panels Omega', Y', Psi', Z' (PanelKind order): k rows each, ld = s (null at the root)
 };
 
 struct SweepArgs {
@@ -47,6 +41,7 @@ struct SweepArgs {
   const PanelSrc* src;
   int32_t nboxes, k, s, mmax, mmin;
   int32_t root;   // 1: only W = Y Omega^dagger of each box (written to D)
+  int32_t mixed;  // 1: split-precision bulk products in the tail kernels
   int32_t* flag;
 };
 
@@ -75,8 +70,9 @@ hipError_t prepare_side_kernels();
 hipError_t launch_lq(const SweepArgs& a, hipStream_t st);
 // truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
 hipError_t launch_col(const SweepArgs& a, hipStream_t st);
-hipError_t launch_combine(const SweepArgs& a, hipStream_t st);
-hipError_t launch_parent(const SweepArgs& a, hipStream_t st);
+// the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c)
+size_t tail_workspace(int dld, int k);
+hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_dense_small(const double* A, int64_t lda, int32_t transA, const double* Bm, int64_t ldb,

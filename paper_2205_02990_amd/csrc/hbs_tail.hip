@@ -1,0 +1,185 @@
+// The per-box products that follow the bases U_tau, V_tau on one level:
+// D_tau (eq. d_tau_formula) and the four k x s blocks each child hands to its
+// parent (eq. omega_tau_and_y_tau; Psi and Z as in Algorithm 2).
+//
+// With W = Y_tau Omega_tau^dagger and X = Z_tau Psi_tau^dagger, eq.
+// d_tau_formula reads D = W - U T with
+//   E = (I - V V^*) X U,   T = U^* W - E^*.
+// Since U^* U = V^* V = I, the two products that eq. omega_tau_and_y_tau
+// takes with D simplify:
+//   U^* D = U^* W - T = E^*,         so U^* (Y - D Omega) = U^* Y - E^* Omega,
+//   D V   = W V - U U^* W V =: H,    so V^* (Z - D^* Psi) = V^* Z - H^* Psi,
+// and the parent blocks no longer wait for D.  Three launches per level:
+//   tail_a  F = X U, Q = W V, T0 = U^* W, and the bulk blocks V^* Omega,
+//           U^* Y, U^* Psi, V^* Z (written to the parent panels);
+//   tail_b  G = V^* F, G2 = U^* Q, E = F - V G, H = Q - U G2, T = T0 - E^*;
+//   tail_c  D = W - U T, and the parent blocks' corrections - E^* Omega,
+//           - H^* Psi.
+// The bulk blocks (every product with a test or sample panel) run in FP64
+// on the matrix cores, or split-precision (sliced_lt) when the batch asks
+// for it; everything that forms D stays FP64.
+#include "hbs_gemm.h"
+#include "hbs_internal.h"
+
+namespace hbs {
+namespace {
+
+constexpr int kSlices = 7;  // 49 bits of every operand: about 1e-14 relative per product
+
+template <bool MIXED>
+struct TailSmem;
+template <>
+struct TailSmem<false> {
+  MfmaSmem<16> g;
+};
+template <>
+struct TailSmem<true> {
+  union {
+    MfmaSmem<16> g;
+    SliceSmem<kSlices> sl;
+  };
+};
+
+// Workspace of one box: F | Q | E | H (dld x k each) | T0 | T (k x dld each) | G | G2 (k x k).
+struct TailWs {
+  double *F, *Q, *E, *H, *T0, *T, *G, *G2;
+  __device__ TailWs(double* base, int dld, int k) {
+    const int64_t mk = (int64_t)dld * k;
+    F = base;
+    Q = F + mk;
+    E = Q + mk;
+    H = E + mk;
+    T0 = H + mk;
+    T = T0 + mk;
+    G = T + mk;
+    G2 = G + (int64_t)k * k;
+  }
+};
+
+// C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
+template <bool MIXED>
+__device__ __forceinline__ void bulk(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
+                            const double* R, int64_t ldr, double beta, const double* C0, int64_t ldc0, double* C,
+                            int64_t ldc) {
+  if constexpr (MIXED)
+    sliced_lt<kSlices>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
+  else
+    mfma_gemm<16>(M, N, K, alpha, L, 1, ldl, R, ldr, 1, beta, C0, ldc0, C, ldc, sm.g);
+}
+
+// FP64 product by the workgroup of either tail variant
+template <bool MIXED>
+__device__ __forceinline__ void dgemm(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* A, int64_t sar,
+                             int64_t sac, const double* B, int64_t sbr, int64_t sbc, double beta, const double* C0,
+                             int64_t ldc0, double* C, int64_t ldc) {
+  mfma_gemm<16, MIXED ? kSliceThreads : kGemmThreads>(M, N, K, alpha, A, sar, sac, B, sbr, sbc, beta, C0, ldc0, C,
+                                                      ldc, sm.g);
+}
+
+template <bool MIXED>
+constexpr int tail_threads() { return MIXED ? kSliceThreads : kGemmThreads; }
+
+// grid (boxes, 3 mt + 4 st): mt = row tiles of the box, st = 64-column tiles of s
+template <bool MIXED>
+__global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs a) {
+  __shared__ TailSmem<MIXED> sm;
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
+  const int mt = (a.mmax + 63) / 64;
+  const int y = blockIdx.y;
+  if (y >= 3 * mt) {
+    const int st = (s + 63) / 64;
+    const int q = y - 3 * mt, which = q / st, c0 = (q % st) * 64;
+    if (c0 >= s) return;
+    // which is the PanelKind: V^* Omega, U^* Y, U^* Psi, V^* Z
+    const PanelSrc& ps = a.src[bx.src];
+    const int64_t ld = ps.ld;
+    const bool useV = (which == kOm) || (which == kZ);
+    const double* L = useV ? bx.V : bx.U;
+    const double* P = ps.p[which] + bx.row0 * ld + c0;
+    bulk<MIXED>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
+    return;
+  }
+  const int which = y / mt, r0 = (y % mt) * 64;
+  if (r0 >= m) return;
+  const int nr = min(64, m - r0);
+  TailWs ws(bx.T, dld, k);
+  if (which == 0)  // F = X U (rows r0..)
+    dgemm<MIXED>(sm, nr, k, m, 1.0, bx.X + (int64_t)r0 * dld, dld, 1, bx.U, k, 1, 0.0, nullptr, 0,
+                 ws.F + (int64_t)r0 * k, k);
+  else if (which == 1)  // Q = W V
+    dgemm<MIXED>(sm, nr, k, m, 1.0, bx.W + (int64_t)r0 * dld, dld, 1, bx.V, k, 1, 0.0, nullptr, 0,
+                 ws.Q + (int64_t)r0 * k, k);
+  else  // T0 = U^* W (columns r0..)
+    dgemm<MIXED>(sm, k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld);
+}
+
+// grid (boxes)
+__global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
+  __shared__ MfmaSmem<16> sm;
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const int m = bx.m, k = a.k, dld = bx.dld;
+  TailWs ws(bx.T, dld, k);
+  mfma_gemm<16>(k, k, m, 1.0, bx.V, 1, k, ws.F, k, 1, 0.0, nullptr, 0, ws.G, k, sm);    // G = V^* F
+  mfma_gemm<16>(k, k, m, 1.0, bx.U, 1, k, ws.Q, k, 1, 0.0, nullptr, 0, ws.G2, k, sm);   // G2 = U^* Q
+  mfma_gemm<16>(m, k, k, -1.0, bx.V, k, 1, ws.G, k, 1, 1.0, ws.F, k, ws.E, k, sm);      // E = F - V G
+  mfma_gemm<16>(m, k, k, -1.0, bx.U, k, 1, ws.G2, k, 1, 1.0, ws.Q, k, ws.H, k, sm);     // H = Q - U G2
+  for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {                          // T = T0 - E^*
+    const int i = idx / m, j = idx % m;
+    ws.T[i * dld + j] = ws.T0[i * dld + j] - ws.E[j * k + i];
+  }
+}
+
+// grid (boxes, mt^2 + 2 st)
+template <bool MIXED>
+__global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs a) {
+  __shared__ TailSmem<MIXED> sm;
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
+  const int mt = (a.mmax + 63) / 64;
+  const int y = blockIdx.y;
+  TailWs ws(bx.T, dld, k);
+  if (y < mt * mt) {  // D = W - U T, one 64 x 64 tile
+    const int r0 = (y / mt) * 64, c0 = (y % mt) * 64;
+    if (r0 >= m || c0 >= m) return;
+    dgemm<MIXED>(sm, min(64, m - r0), min(64, m - c0), k, -1.0, bx.U + (int64_t)r0 * k, k, 1, ws.T + c0, dld, 1,
+                 1.0, bx.W + (int64_t)r0 * dld + c0, dld, bx.D + (int64_t)r0 * dld + c0, dld);
+    return;
+  }
+  const int st = (s + 63) / 64;
+  const int q = y - mt * mt, which = q / st, c0 = (q % st) * 64;
+  if (c0 >= s) return;
+  const PanelSrc& ps = a.src[bx.src];
+  const int64_t ld = ps.ld;
+  // which 0: Y' = U^* Y - E^* Omega;  which 1: Z' = V^* Z - H^* Psi (in place)
+  const double* L = which ? ws.H : ws.E;
+  const double* P = ps.p[2 * which] + bx.row0 * ld + c0;  // Omega or Psi
+  double* out = bx.np[2 * which + 1] + c0;                 // Y' or Z'
+  bulk<MIXED>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
+}
+
+}  // namespace
+
+size_t tail_workspace(int dld, int k) { return 6 * (size_t)dld * k + 2 * (size_t)k * k; }
+
+hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
+  const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
+  if (part == 0) {
+    const dim3 grid(a.nboxes, 3 * mt + 4 * sct);
+    if (a.mixed)
+      hipLaunchKernelGGL(tail_a_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(tail_a_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
+  } else if (part == 1) {
+    hipLaunchKernelGGL(tail_b_kernel, dim3(a.nboxes), dim3(kGemmThreads), 0, st, a);
+  } else {
+    const dim3 grid(a.nboxes, mt * mt + 2 * sct);
+    if (a.mixed)
+      hipLaunchKernelGGL(tail_c_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(tail_c_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace hbs

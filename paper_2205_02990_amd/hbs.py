@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhbs.so")
 
 HBS_OK, HBS_EINVAL, HBS_ENOMEM, HBS_EDEVICE, HBS_ENUMERIC, HBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-PRECISION = {"fp64": 0, "fp32_split": 1, "bf16": 2}
+PRECISION = {"fp64": 0, "split": 1, "fp32_split": 1, "bf16": 2}
 
 _lib = None
 _hip = None
@@ -221,7 +221,7 @@ class Factors:
             self._h = None
 
 
-PROFILE_CLASSES = ("lq", "col", "combine", "parent", "root")
+PROFILE_CLASSES = ("lq", "col", "tail_a", "tail_b", "tail_c", "root")
 
 
 def _profile_read(h) -> dict:

@@ -102,6 +102,28 @@ def test_compress_matches_oracle(hbs, n, k, leaf, s):
         assert np.all(U[t, m:] == 0) and np.all(D[t, m:] == 0) and np.all(D[t, :, m:] == 0)
 
 
+@pytest.mark.parametrize("n,k,leaf,s", CASES)
+def test_split_precision_matches_oracle(hbs, n, k, leaf, s):
+    """Split-precision bulk products (7-bit integer slices on the int8 matrix
+    cores): the FP64 oracle's operator to 1e-10, bases still orthonormal."""
+    print(f"[parity] split compress n={n} k={k} leaf={leaf} s={s}", flush=True)
+    case = synthetic_case(n, k, leaf, s)
+    orc = ohbs.compress(case["levels"], k, case["Om"], case["Y"], case["Ps"], case["Z"])
+    tree = hbs.Tree(n, leaf)
+    f = hbs.compress(tree, k, dev(case["Om"]), dev(case["Y"]), dev(case["Ps"]), dev(case["Z"]), precision="split")
+    f.check()
+    G = case["G"]
+    e = rel(host(f.apply(dev(G))), ohbs.apply(orc, G))
+    et = rel(host(f.apply(dev(G), transpose=True)), ohbs.apply(orc, G, transpose=True))
+    print(f"[parity] split vs oracle {e:.2e} (transpose {et:.2e})", flush=True)
+    assert e <= 1e-10 and et <= 1e-10
+    assert rel(host(f.apply(dev(G))), ohbs.apply(case["gen"], G)) <= 1e-10
+    for lev in range(1, tree.levels + 1):
+        U = f.level(lev)["U"]
+        Gm = torch.matmul(U.transpose(1, 2).contiguous(), U)
+        assert float((Gm - torch.eye(k, dtype=Gm.dtype, device=Gm.device)).abs().max()) <= 1e-13
+
+
 def test_root_only_least_squares(hbs):
     """L = 0: the whole matrix is the root block D^(0) = Y Omega^dagger."""
     rng = np.random.default_rng(11)
@@ -172,6 +194,27 @@ def test_logkernel_compress_matches_oracle(hbs):
     # both sides approximate A to err_orc; they agree far below it
     assert rel(got, ref) <= max(1e-12, 0.1 * err_orc)
     assert rel(got, A @ G) <= 2 * err_orc + 1e-13
+
+
+def test_logkernel_compress_split_matches_oracle(hbs):
+    """The same log-kernel problem on the split-precision path."""
+    n, k, leaf, s = 2048, 50, 100, 160
+    x, y = inputs.ellipse_points(n)
+    rs = inputs.streams(2, extra=(n,))
+    Om, Ps = inputs.gaussian(rs[1], n, s), inputs.gaussian(rs[2], n, s)
+    A = olog.rows(x, y, np.arange(n))
+    Y, Z = A @ Om, A @ Ps
+    orc = ohbs.compress(otree.cluster_tree(n, leaf), k, Om, Y, Ps, Z)
+    tree = hbs.Tree(n, leaf)
+    f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z), precision="split")
+    f.check()
+    G = inputs.probes(rs[3], n)
+    ref = ohbs.apply(orc, G)
+    got = host(f.apply(dev(G)))
+    err_orc = rel(ref, A @ G)
+    print(f"[parity] log kernel split: vs oracle {rel(got, ref):.2e}, oracle vs A {err_orc:.2e}", flush=True)
+    assert rel(got, ref) <= max(1e-10, 0.1 * err_orc)
+    assert rel(got, A @ G) <= 2 * err_orc + 1e-10
 
 
 def test_numeric_flag_on_nonfinite_input(hbs):
