@@ -12,7 +12,8 @@
 // and the parent blocks no longer wait for D.  Three launches per level:
 //   tail_a  F = X U, Q = W V, T0 = U^* W, and the bulk blocks V^* Omega,
 //           U^* Y, U^* Psi, V^* Z (written to the parent panels);
-//   tail_b  G = V^* F, G2 = U^* Q, E = F - V G, H = Q - U G2, T = T0 - E^*;
+//   tail_b  G = V^* F, G2 = U^* Q, E = F - V G, H = Q - U G2, T = T0 - E^*
+//           (two chains, split by rows);
 //   tail_c  D = W - U T, and the parent blocks' corrections - E^* Omega,
 //           - H^* Psi.
 // The bulk blocks (every product with a test or sample panel) run in FP64
@@ -40,9 +41,10 @@ struct TailSmem<true> {
   };
 };
 
-// Workspace of one box: F | Q | E | H (dld x k each) | T0 | T (k x dld each) | G | G2 (k x k).
+// Workspace of one box: F | Q | E | H (dld x k each) | T0 | T (k x dld each) |
+// G: one k x k product per chain and row block (2 ceil(dld / 64) of them).
 struct TailWs {
-  double *F, *Q, *E, *H, *T0, *T, *G, *G2;
+  double *F, *Q, *E, *H, *T0, *T, *G;
   __device__ TailWs(double* base, int dld, int k) {
     const int64_t mk = (int64_t)dld * k;
     F = base;
@@ -52,7 +54,6 @@ struct TailWs {
     T0 = H + mk;
     T = T0 + mk;
     G = T + mk;
-    G2 = G + (int64_t)k * k;
   }
 };
 
@@ -114,20 +115,33 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs
     dgemm<MIXED>(sm, k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld);
 }
 
-// grid (boxes)
+// grid (boxes, 2 nrb): chain 0 forms G = V^* F, then rows of E = F - V G and
+// the matching columns of T = T0 - E^*; chain 1 forms G2 = U^* Q, then rows of
+// H = Q - U G2.  With nrb > 1 (levels of few boxes) every 64-row block
+// recomputes its chain's k x k product (into its own slot) so that the blocks
+// run independently.
+template <int TK>
 __global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
-  __shared__ MfmaSmem<16> sm;
+  __shared__ MfmaSmem<TK> sm;
   const BoxDesc& bx = a.box[blockIdx.x];
   const int m = bx.m, k = a.k, dld = bx.dld;
+  const int nrb = gridDim.y / 2;  // row blocks per chain: 1, or one per 64 rows
+  const int chain = blockIdx.y / nrb, rb = blockIdx.y % nrb, r0 = rb * 64;
+  if (r0 >= m) return;
+  const int nr = (nrb == 1) ? m : min(64, m - r0);
   TailWs ws(bx.T, dld, k);
-  mfma_gemm<16>(k, k, m, 1.0, bx.V, 1, k, ws.F, k, 1, 0.0, nullptr, 0, ws.G, k, sm);    // G = V^* F
-  mfma_gemm<16>(k, k, m, 1.0, bx.U, 1, k, ws.Q, k, 1, 0.0, nullptr, 0, ws.G2, k, sm);   // G2 = U^* Q
-  mfma_gemm<16>(m, k, k, -1.0, bx.V, k, 1, ws.G, k, 1, 1.0, ws.F, k, ws.E, k, sm);      // E = F - V G
-  mfma_gemm<16>(m, k, k, -1.0, bx.U, k, 1, ws.G2, k, 1, 1.0, ws.Q, k, ws.H, k, sm);     // H = Q - U G2
-  for (int idx = threadIdx.x; idx < k * m; idx += blockDim.x) {                          // T = T0 - E^*
-    const int i = idx / m, j = idx % m;
-    ws.T[i * dld + j] = ws.T0[i * dld + j] - ws.E[j * k + i];
-  }
+  const double* B1 = chain ? bx.U : bx.V;   // basis of the k x k product
+  const double* B2 = chain ? ws.Q : ws.F;   // its m x k partner
+  double* Gs = ws.G + (int64_t)(chain * nrb + rb) * k * k;
+  double* Out = chain ? ws.H : ws.E;
+  mfma_gemm<TK>(k, k, m, 1.0, B1, 1, k, B2, k, 1, 0.0, nullptr, 0, Gs, k, sm);
+  mfma_gemm<TK>(nr, k, k, -1.0, B1 + (int64_t)r0 * k, k, 1, Gs, k, 1, 1.0, B2 + (int64_t)r0 * k, k,
+                Out + (int64_t)r0 * k, k, sm);
+  if (chain == 0)
+    for (int idx = threadIdx.x; idx < k * nr; idx += blockDim.x) {
+      const int i = idx / nr, j = r0 + idx % nr;
+      ws.T[i * dld + j] = ws.T0[i * dld + j] - ws.E[j * k + i];
+    }
 }
 
 // grid (boxes, mt^2 + 2 st)
@@ -160,7 +174,9 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs
 
 }  // namespace
 
-size_t tail_workspace(int dld, int k) { return 6 * (size_t)dld * k + 2 * (size_t)k * k; }
+size_t tail_workspace(int dld, int k) {
+  return 6 * (size_t)dld * k + 2 * (size_t)((dld + 63) / 64) * k * k;
+}
 
 hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
@@ -171,7 +187,11 @@ hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
     else
       hipLaunchKernelGGL(tail_a_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
   } else if (part == 1) {
-    hipLaunchKernelGGL(tail_b_kernel, dim3(a.nboxes), dim3(kGemmThreads), 0, st, a);
+    // few boxes: latency bound, row blocks in parallel and deeper K chunks
+    if (a.nboxes < 256)
+      hipLaunchKernelGGL(tail_b_kernel<32>, dim3(a.nboxes, 2 * mt), dim3(kGemmThreads), 0, st, a);
+    else
+      hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
   } else {
     const dim3 grid(a.nboxes, mt * mt + 2 * sct);
     if (a.mixed)
