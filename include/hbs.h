@@ -47,10 +47,11 @@ typedef enum {
   HBS_FP64 = 0,           /* every product in FP64                              */
   HBS_FP32_SPLIT = 1,     /* split precision: every product with a test or
                            * sample block from exact 7-bit integer slices on
-                           * the int8 matrix cores, recombined in FP64 (about
-                           * 1e-14 relative per product); QR, bases, solves
+                           * the int8 matrix cores, recombined in FP64 (eight
+                           * slices: FP64-level error per product); QR, bases, solves
                            * and D_tau stay FP64                               */
-  HBS_BF16 = 2            /* log-kernel sampler only: BF16 operands, FP32 sums  */
+  HBS_BF16 = 2            /* log-kernel sampler only: BF16 hi/lo operand pairs,
+                           * FP32 sums                                         */
 } hbs_precision;
 
 typedef struct hbs_tree hbs_tree;        /* host-only, immutable after create */
@@ -197,8 +198,10 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
  * Writes Y = A Omega and Z = A^* Psi = A Psi (A is symmetric); Omega, Psi, Y,
  * Z are n x s with leading dimension ld.  The kernel is never stored: every
  * entry is formed on the fly inside the matrix-core product.  `prec`:
- * HBS_FP64 (FP64 entries and FP64 matrix-core products) or HBS_BF16 (BF16
- * entries and samples, FP32 accumulation). */
+ * HBS_FP64 (FP64 entries and FP64 matrix-core products) or HBS_BF16 (entries
+ * formed in FP32; entries and test-matrix values each carried as a BF16 pair
+ * hi + lo, three BF16 matrix-core products per pair, FP32 accumulation: about
+ * 1e-5 relative error in Y and Z).  HBS_FP32_SPLIT is HBS_EUNSUPPORTED here. */
 hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, const double* Omega,
                                 const double* Psi, double* Y, double* Z, int32_t s, int64_t ld,
                                 hbs_precision prec, void* hip_stream);

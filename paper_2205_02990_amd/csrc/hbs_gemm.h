@@ -132,7 +132,7 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, double alpha, con
 // t = sum_p q_p 2^(-7p) + a remainder below 2^(-7S); each q_p lies in
 // [-127, 127].  Products of slice pairs (p, q) with p + q <= S + 1 are exact
 // in 32-bit integer sums (at most S pairs per diagonal: |sum| <= S K 127^2,
-// below 2^31 for K < 2^31 / (S 127^2), 19000 at S = 7) and
+// below 2^31 for K < 2^31 / (S 127^2), 16600 at S = 8) and
 // are accumulated per diagonal p + q; the diagonals are combined in FP64:
 //   C(i, j) ~ 2^(e_i + f_j) sum_d 2^(-7 d) acc_d(i, j).
 // Dropped pairs and slice remainders bound the error of each entry by about
@@ -144,17 +144,27 @@ __device__ __forceinline__ void mfma_gemm(int M, int N, int K, double alpha, con
 // receives C(4 (l / 16) + r, l % 16) in element r.  Called by the 512
 // threads of a workgroup; each of its 8 waves owns a 16 x 32 strip of each
 // 64 x 64 output tile.
-constexpr int kSliceK = 64;                 // contracted indices per LDS chunk
-constexpr int kSliceRow = kSliceK / 4 + 4;  // int32 words per slice row (16 bytes of padding)
-constexpr int kSliceGroups = kSliceThreads / 64;     // contracted-index groups in staging
-constexpr int kSlicePer = kSliceK / kSliceGroups;    // contracted indices per staging thread
+constexpr int kSliceK = 64;                       // contracted indices per LDS chunk
+constexpr int kSliceRow = kSliceK / 4;            // int32 words per slice row
+constexpr int kSliceGroups = kSliceThreads / 64;  // contracted-index groups in staging
+constexpr int kSlicePer = kSliceK / kSliceGroups; // contracted indices per staging thread
+
+// The 16-byte blocks of a slice row are stored XOR-swizzled by row so that
+// the 16 rows one MFMA operand read touches fall in distinct LDS banks.
+__device__ __forceinline__ int slice_word(int row, int word) {
+  return ((((word >> 2) ^ (row >> 2)) & 3) << 2) | (word & 3);
+}
 
 template <int S>
 struct SliceSmem {
-  int32_t As[S][64][kSliceRow];  // As[p][i][kk / 4]: four slices q_p of L(kk, i) per word
-  int32_t Bs[S][64][kSliceRow];
-  double red[2][kSliceGroups][64];  // partial maxima
-  int ea[64], eb[64];               // scale exponents
+  union {
+    struct {
+      int32_t As[S][64][kSliceRow];  // As[p][i][.]: four slices q_p of L(kk, i) per word
+      int32_t Bs[S][64][kSliceRow];
+    } q;
+    double red[2][kSliceGroups][64];  // partial maxima (before any slicing)
+  } u;
+  int ea[64], eb[64];                 // scale exponents
 };
 
 // Cut 4 values (scaled by 2^-e) into S slices, one word of packed bytes each.
@@ -194,8 +204,9 @@ __device__ __forceinline__ void slice_stage(const double* __restrict__ X, int64_
     }
     int32_t sw[S];
     slice4<S>(x, e, sw);
+    const int word = slice_word(c, (kSlicePer / 4) * g + w);
 #pragma unroll
-    for (int p = 0; p < S; ++p) dst[p][c][(kSlicePer / 4) * g + w] = sw[p];
+    for (int p = 0; p < S; ++p) dst[p][c][word] = sw[p];
   }
 }
 
@@ -219,14 +230,14 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
           ma = fmax(ma, oki ? fabs(va) : 0.0);
           mb = fmax(mb, okj ? fabs(vb) : 0.0);
         }
-        sm.red[0][g][c] = ma;
-        sm.red[1][g][c] = mb;
+        sm.u.red[0][g][c] = ma;
+        sm.u.red[1][g][c] = mb;
         __syncthreads();
         if (tid < 128) {
           const int h = tid >> 6;
           double mx = 0.0;
 #pragma unroll
-          for (int q = 0; q < kSliceGroups; ++q) mx = fmax(mx, sm.red[h][q][c]);
+          for (int q = 0; q < kSliceGroups; ++q) mx = fmax(mx, sm.u.red[h][q][c]);
           int e = 0;
           (void)frexp(mx, &e);  // mx = f 2^e, f in [0.5, 1); 0 for mx = 0
           (h ? sm.eb : sm.ea)[c] = e;
@@ -239,17 +250,19 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
 #pragma unroll
         for (int d = 0; d < S; ++d) acc[b][d] = gemm_i4{0, 0, 0, 0};
       for (int k0 = 0; k0 < K; k0 += kSliceK) {
-        slice_stage<S>(L, ldl, i0, M, K, k0, c, g, sm.ea[c], sm.As);
-        slice_stage<S>(R, ldr, j0, N, K, k0, c, g, sm.eb[c], sm.Bs);
+        slice_stage<S>(L, ldl, i0, M, K, k0, c, g, sm.ea[c], sm.u.q.As);
+        slice_stage<S>(R, ldr, j0, N, K, k0, c, g, sm.eb[c], sm.u.q.Bs);
         __syncthreads();
         gemm_i4 ap[S];
+        const int wa = slice_word(rb + li, 4 * lk);
 #pragma unroll
-        for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.As[p][rb + li][4 * lk]);
+        for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.As[p][rb + li][wa]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
           gemm_i4 bq[S];
+          const int wb = slice_word(cb + 16 * b + li, 4 * lk);
 #pragma unroll
-          for (int q = 0; q < S; ++q) bq[q] = *reinterpret_cast<const gemm_i4*>(&sm.Bs[q][cb + 16 * b + li][4 * lk]);
+          for (int q = 0; q < S; ++q) bq[q] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
 #pragma unroll
           for (int p = 0; p < S; ++p)
 #pragma unroll

@@ -784,7 +784,7 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
 hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, const double* Omega, const double* Psi,
                                 double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, void* hip_stream) {
   if (n < 1 || s < 1 || ld < s || !x || !y || !Omega || !Psi || !Y || !Z) return HBS_EINVAL;
-  if (prec != HBS_FP64) return HBS_EUNSUPPORTED;
+  if (prec != HBS_FP64 && prec != HBS_BF16) return HBS_EUNSUPPORTED;
   HIP_TRY(hbs::launch_logkernel(n, x, y, Omega, Psi, Y, Z, s, ld, prec, (hipStream_t)hip_stream));
   return HBS_OK;
 }

@@ -12,6 +12,16 @@
 //   A operand: lane l holds A(l % 16, l / 16)
 //   B operand: lane l holds B(l / 16, l % 16)
 //   result:    lane l, element r holds C(l / 16 + 4 r, l % 16)
+//
+// BF16 path: v_mfma_f32_16x16x32_bf16 with FP32 accumulation.  Every kernel
+// entry (formed in FP32) and every test-matrix entry is carried as a pair of
+// BF16 values hi + lo (hi = bf16(v), lo = bf16(v - hi): 16 significant bits),
+// and each product is the sum of the three partial products hi hi, hi lo,
+// lo hi, so the samples carry about 1e-5 relative error instead of the 4e-3
+// of plain BF16 operands.  A workgroup owns 64 rows and 208 columns of the
+// concatenation [Omega Psi], so each kernel entry it forms serves 208 columns.
+// Lanes l supply 8 consecutive points (8 (l / 16) + r) of row l % 16 (A) and
+// of column l % 16 (B); the result is C(4 (l / 16) + r, l % 16).
 #include "hbs_internal.h"
 
 namespace hbs {
@@ -89,10 +99,98 @@ __global__ void __launch_bounds__(256) logkernel_f64(int64_t n, const double* __
   }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTB = 13;           // 16-column tiles per workgroup
+constexpr int kColsB = 16 * kTB;  // columns of [Omega Psi] per workgroup
+constexpr int kKB = 32;           // points per chunk (the MFMA depth)
+constexpr int kBPad = kKB + 8;    // staged BF16 values per column (16 bytes of padding)
+
+__device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
+  hi = (__bf16)v;
+  lo = (__bf16)(v - (float)hi);
+}
+
+__global__ void __launch_bounds__(256) logkernel_bf16(int64_t n, const double* __restrict__ x,
+                                                      const double* __restrict__ y, const double* __restrict__ Om,
+                                                      const double* __restrict__ Ps, double* __restrict__ Yo,
+                                                      double* __restrict__ Zo, int32_t s, int64_t ld) {
+  __shared__ __bf16 Bhi[kColsB][kBPad];
+  __shared__ __bf16 Blo[kColsB][kBPad];
+  __shared__ double xsh[kKB], ysh[kKB];
+  const int c0 = blockIdx.y * kColsB;  // first column of [Omega Psi]
+  const int ncol = min(kColsB, 2 * s - c0);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row = (int64_t)blockIdx.x * kRows + wave * 16 + (lane & 15);  // A-operand row of this lane
+  const bool rowok = row < n;
+  const double xi = rowok ? x[row] : 0.0, yi = rowok ? y[row] : 0.0;
+  f32x4 acc[kTB];
+#pragma unroll
+  for (int t = 0; t < kTB; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  for (int64_t j0 = 0; j0 < n; j0 += kKB) {
+    __syncthreads();
+    for (int idx = tid; idx < kKB * kColsB; idx += 256) {
+      const int jj = idx / kColsB, cc = idx % kColsB;
+      const int64_t j = j0 + jj;
+      const int c = c0 + cc;
+      double v = 0.0;
+      if (j < n && cc < ncol) v = (c < s) ? Om[j * ld + c] : Ps[j * ld + (c - s)];
+      split_bf16((float)v, Bhi[cc][jj], Blo[cc][jj]);
+    }
+    if (tid < kKB) {
+      const int64_t j = j0 + tid;
+      xsh[tid] = (j < n) ? x[j] : 0.0;
+      ysh[tid] = (j < n) ? y[j] : 0.0;
+    }
+    __syncthreads();
+    bf16x8 ah, al;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int jj = 8 * (lane >> 4) + r;
+      const int64_t j = j0 + jj;
+      const double dx = xi - xsh[jj], dy = yi - ysh[jj];
+      const float a = (rowok && j < n && j != row) ? 0.5f * logf((float)(dx * dx + dy * dy)) : 0.f;
+      __bf16 h, l;
+      split_bf16(a, h, l);
+      ah[r] = h;
+      al[r] = l;
+    }
+#pragma unroll
+    for (int t = 0; t < kTB; ++t) {
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(&Bhi[t * 16 + (lane & 15)][8 * (lane >> 4)]);
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(&Blo[t * 16 + (lane & 15)][8 * (lane >> 4)]);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
+    }
+  }
+  const int64_t rbase = (int64_t)blockIdx.x * kRows + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+  for (int t = 0; t < kTB; ++t) {
+    const int cc = t * 16 + (lane & 15);
+    if (cc < ncol) {
+      const int c = c0 + cc;
+      double* out = (c < s) ? Yo + c : Zo + (c - s);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t rr = rbase + r;
+        if (rr < n) out[rr * ld] = (double)acc[t][r];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_logkernel(int64_t n, const double* x, const double* y, const double* Om, const double* Ps,
                             double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, hipStream_t st) {
+  if (prec == HBS_BF16) {
+    dim3 grid((unsigned)((n + kRows - 1) / kRows), (2 * s + kColsB - 1) / kColsB);
+    hipLaunchKernelGGL(logkernel_bf16, grid, dim3(256), 0, st, n, x, y, Om, Ps, Y, Z, s, ld);
+    return hipGetLastError();
+  }
   if (prec != HBS_FP64) return hipErrorInvalidValue;
   const int nchunk = (s + kCols - 1) / kCols;
   dim3 grid((unsigned)((n + kRows - 1) / kRows), 2 * nchunk);

@@ -25,7 +25,7 @@
 namespace hbs {
 namespace {
 
-constexpr int kSlices = 7;  // 49 bits of every operand: about 1e-14 relative per product
+constexpr int kSlices = 8;  // 56 bits of every operand: FP64-level error per product
 
 template <bool MIXED>
 struct TailSmem;

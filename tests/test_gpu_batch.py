@@ -125,20 +125,25 @@ def test_batch512_full_size(hbs):
         Z.append(dev(ohbs.apply(gen, ps, transpose=True)))
         trees.append(hbs.Tree(x["n"], x["leaf_max"]))
     print("[batch512] inputs ready; compressing", flush=True)
-    b = hbs.Batch(trees, [x["k"] for x in spec], [x["s"] for x in spec])
-    b.compress(Om, Y, Ps, Z)
-    f0 = b.factors(0)
-    f0.check()
-    worst = 0.0
-    for i, x in enumerate(spec):
-        f = b.factors(i)
-        AG = ohbs.apply(gens[i][1], G[i])
-        e = rel(host(f.apply(dev(G[i]))), AG)
-        worst = max(worst, e)
-        # depth <= 10 here; the method's own rounding growth up the tree keeps
-        # the oracle below 3e-11 at depth 11 with these parameters
-        assert e <= 1e-10, (i, x, e)
-    print(f"[batch512] worst relative apply error vs generator {worst:.3e}", flush=True)
+    ks, ss = [x["k"] for x in spec], [x["s"] for x in spec]
+    worst = {}
+    batches = {}
+    for precision in ("fp64", "split"):
+        b = hbs.Batch(trees, ks, ss, precision)
+        b.compress(Om, Y, Ps, Z)
+        b.factors(0).check()
+        w = 0.0
+        for i, x in enumerate(spec):
+            AG = ohbs.apply(gens[i][1], G[i])
+            e = rel(host(b.factors(i).apply(dev(G[i]))), AG)
+            w = max(w, e)
+        worst[precision] = w
+        batches[precision] = b
+        print(f"[batch512] {precision}: worst relative apply error vs generator {w:.3e}", flush=True)
+    # depth <= 10 here; the method's own rounding growth up the tree keeps
+    # the oracle below 3e-11 at depth 11 with these parameters
+    assert worst["fp64"] <= 1e-10
+    assert worst["split"] <= 1e-10
     order = sorted(range(len(spec)), key=lambda i: spec[i]["n"])
     rng = inputs.streams(wl["id"], 1, extra=(0x5A3,))[0]
     pick = sorted({order[0], order[-1], *rng.choice(len(spec), 2, replace=False).tolist()})
@@ -146,7 +151,8 @@ def test_batch512_full_size(hbs):
         levels, gen, om, ps = gens[i]
         x = spec[i]
         orc = ohbs.compress(levels, x["k"], om, host(Y[i]), ps, host(Z[i]))
-        e = rel(host(b.factors(i).apply(dev(G[i]))), ohbs.apply(orc, G[i]))
-        print(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)}: vs oracle {e:.3e}",
-              flush=True)
-        assert e <= 1e-10
+        OG = ohbs.apply(orc, G[i])
+        e = {p: rel(host(batches[p].factors(i).apply(dev(G[i]))), OG) for p in batches}
+        print(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)}: vs oracle "
+              f"fp64 {e['fp64']:.3e}, split {e['split']:.3e}", flush=True)
+        assert e["fp64"] <= 1e-10 and e["split"] <= 1e-10

@@ -87,6 +87,40 @@ def test_logkernel_full_size(hbs, name):
     check_orthonormal(f, tree, k)
 
 
+@pytest.mark.timeout(600)
+def test_logkernel_n262144_precision_paths(hbs):
+    """The three precision paths on the N = 2^18 log-kernel workload, against
+    dense oracle rows: FP64 samples with the split-precision sweep, and BF16
+    samples with the FP64 sweep (bounds 1e-9 and 1e-4; the FP64 path itself
+    is checked above)."""
+    wl = inputs.WORKLOADS["logkernel_ellipse_n262144_k64"]
+    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
+    rs = inputs.streams(wl["id"])
+    x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
+    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
+    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
+    xd, yd, Omd, Psd = dev(x), dev(y), dev(Om), dev(Ps)
+    R = np.sort(rs[inputs.STREAM_ROWS].choice(n, 256, replace=False))
+    G = inputs.probes(rs[inputs.STREAM_PROBES], n, 8)
+    AG_R = olog.sample(x, y, G, R)
+    tree = hbs.Tree(n, leaf)
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd)
+    f = hbs.compress(tree, k, Omd, Yd, Psd, Zd, precision="split")
+    f.check()
+    e_split = rel(f.apply(dev(G)).cpu().numpy()[R], AG_R)
+    del f
+    Yb, Zb = hbs.sample_logkernel(xd, yd, Omd, Psd, precision="bf16")
+    Rd = torch.from_numpy(R).cuda()
+    e_samp = rel(Yb[Rd].cpu().numpy(), olog.sample(x, y, Om, R))
+    f = hbs.compress(tree, k, Omd, Yb, Psd, Zb)
+    f.check()
+    e_bf16 = rel(f.apply(dev(G)).cpu().numpy()[R], AG_R)
+    print(f"[fullsize] N={n}: split sweep {e_split:.3e}; bf16 sampler rows {e_samp:.3e}, "
+          f"bf16 samples + FP64 sweep {e_bf16:.3e}", flush=True)
+    assert e_split <= 1e-9
+    assert e_samp <= 1e-4 and e_bf16 <= 1e-4
+
+
 @pytest.mark.timeout(900)
 def test_exact_rank_n4194304_full_size(hbs):
     """Exact recovery of the 16-level exact-rank HBS matrix from samples that
@@ -127,6 +161,16 @@ def test_exact_rank_n4194304_full_size(hbs):
     AtG = ohbs.apply(fac, G, transpose=True)
     assert rel(f.apply(dev(G), transpose=True).cpu().numpy(), AtG) <= 5e-9
     check_orthonormal(f, tree, k)
+    del f
+    fs = hbs.Factors.create(tree, k, s, "split")
+    fs.compress_into(Omd, Yd, Psd, Zd)
+    fs.check()
+    err_s = rel(fs.apply(dev(G)).cpu().numpy(), AG)
+    print(f"[fullsize] exact-rank N={n}: split path, relative apply error vs the generator {err_s:.3e}", flush=True)
+    # eight 7-bit slices give the split products FP64-level error, so the
+    # split path meets the FP64 path's bound
+    assert err_s <= 5e-9
+    del fs
     # the library's Algorithm 1 on the imported generator agrees with the oracle's
     lv = {}
     for l in range(1, tree.levels + 1):

@@ -173,6 +173,19 @@ def test_logkernel_sampler_matches_dense_rows(hbs, n, s):
     assert rel(host(Zg), Zr) <= 1e-13
 
 
+@pytest.mark.parametrize("n,s", [(1000, 58), (257, 160), (2048, 202), (64, 1)])
+def test_logkernel_sampler_bf16(hbs, n, s):
+    """BF16 hi/lo operand pairs with FP32 accumulation: about 1e-5 relative,
+    bound 1e-4; worse than FP64 by construction."""
+    x, y = inputs.ellipse_points(n)
+    rs = inputs.streams(2, extra=(n, s, 16))
+    Om, Ps = inputs.gaussian(rs[1], n, s), inputs.gaussian(rs[2], n, s)
+    Yg, Zg = hbs.sample_logkernel(dev(x), dev(y), dev(Om), dev(Ps), precision="bf16")
+    ey, ez = rel(host(Yg), olog.sample(x, y, Om)), rel(host(Zg), olog.sample(x, y, Ps))
+    print(f"[parity] bf16 sampler n={n} s={s}: {ey:.2e} {ez:.2e}", flush=True)
+    assert ey <= 1e-4 and ez <= 1e-4
+
+
 def test_logkernel_compress_matches_oracle(hbs):
     """General (not exactly HBS) input: the log kernel, k = 50, leaf threshold
     100 (leaves of 64), s = 160, on 2048 ellipse points; samples from the oracle."""
