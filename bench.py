@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--path", default="fp64", choices=["fp64", "split"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subtree-level", type=int, default=4)
+    ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="first run a plain copy kernel over MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -139,6 +142,14 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hbs.load()
+    if args.copy_probe:
+        # plain elementwise copy of a known size: reads and writes MIB MiB each
+        src = torch.ones(args.copy_probe * (1 << 20) // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---- inputs (seeded, host) and samples (GPU black box) -----------------
     rs = inputs.streams(wl["id"])
@@ -150,9 +161,9 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd)  # warm
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)  # warm
     e0.record()
-    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd)
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)
     e1.record()
     torch.cuda.synchronize()
     sampler_ms = e0.elapsed_time(e1)
@@ -230,7 +241,7 @@ def main():
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": args.workload, "N": n, "k": k, "leaf_max": leaf, "leaf": leaf_sizes[0], "s": s,
-                   "levels": tree.levels, "path": args.path},
+                   "levels": tree.levels, "path": args.path, "sampler": args.sampler},
         "roofline": roofline,
         "rel_apply_err": rel_err, "in_sample_err": in_sample,
         "sampler_ms": sampler_ms, "rows_per_s_incl_sampler": n / ((ms_per_step + sampler_ms) / 1e3),
