@@ -4,9 +4,10 @@
 One step = one full compression sweep (Algorithm 2: every level from the
 leaves to the root, all boxes of a level at once) of an N x N matrix from its
 samples {Omega, Y = A Omega, Psi, Z = A^* Psi}, which are resident in HBM when
-the timed region starts.  The samples come from the log-kernel stand-in
-black box (sampler timed separately, like the paper's compression time
-without the matvec).
+the timed region starts (for the batched workload: one sweep over all
+instances).  The samples come from a stand-in black box, timed separately
+like the paper's compression time without the matvec: the log-kernel sampler
+(default workload), or Algorithm 1 on a seeded exact-rank generator.
 
 Output: one JSON line on stdout (rank 0).  Progress goes to stderr.
 """
@@ -82,35 +83,183 @@ def sweep_model(leaf_sizes, k, s):
 # CPU baseline (oracle on a bounded sample)
 # --------------------------------------------------------------------------
 
-def cpu_baseline(wl, x, y, Om, Ps, sub_levels_below_root):
-    """Time the FP64 oracle on the subtree of the first node of level
-    `sub_levels_below_root`: all of that subtree's levels, on its own rows."""
+def _threads():
     import threadpoolctl
-    from oracle import hbs as ohbs
-    from oracle import logkernel as olog
-    from oracle import tree as otree
-    n = wl["n"]
-    full = otree.cluster_tree(n, wl["leaf_max"])
-    a, b = full[sub_levels_below_root][0]
-    rows = np.arange(a, b)
-    t0 = time.perf_counter()
-    G = np.hstack((Om, Ps))
-    YZ = olog.sample(x, y, G, rows)  # samples of the sample rows, formed by the oracle
-    Ys, Zs = YZ[:, :wl["s"]], YZ[:, wl["s"]:]
-    log(f"cpu baseline: oracle samples of rows [{a}, {b}) in {time.perf_counter() - t0:.1f} s")
-    sub = otree.cluster_tree(b - a, wl["leaf_max"])
     info = threadpoolctl.threadpool_info()
-    threads = max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1])
+    return int(max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1]))
+
+
+def cpu_baseline(k, leaf_max, levels, Om, Y, Ps, Z, sub_level, what):
+    """Time the FP64 oracle's Algorithm 2 on the rows of the first node of
+    level `sub_level` (all of that subtree's levels, on its own rows)."""
+    from oracle import hbs as ohbs
+    from oracle import tree as otree
+    a, b = levels[sub_level][0]
+    sub = otree.cluster_tree(b - a, leaf_max)
     t0 = time.perf_counter()
-    ohbs.compress(sub, wl["k"], Om[a:b], Ys, Ps[a:b], Zs)
+    ohbs.compress(sub, k, Om[a:b], Y[a:b], Ps[a:b], Z[a:b])
     dt = time.perf_counter() - t0
-    return {"value": (b - a) / dt, "unit": "rows/s", "cores": int(threads), "kind": "oracle",
-            "sample": (f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of level "
-                       f"{sub_levels_below_root} ({otree.depth(sub)} levels, all its boxes), "
-                       f"{dt:.1f} s; host os.cpu_count()={os.cpu_count()}")}
+    return {"value": (b - a) / dt, "unit": "rows/s", "cores": _threads(), "kind": "oracle",
+            "sample": (f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of level {sub_level} "
+                       f"of {what} ({otree.depth(sub)} levels, all its boxes), {dt:.1f} s; "
+                       f"host os.cpu_count()={os.cpu_count()}")}
 
 
 # --------------------------------------------------------------------------
+# workloads: each returns the problem on the device and how to measure it
+# --------------------------------------------------------------------------
+
+class Problem:
+    pass
+
+
+def setup_logkernel(wl, args, hbs, torch, inputs, dev):
+    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
+    rs = inputs.streams(wl["id"])
+    x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
+    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
+    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
+    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
+    Omd, Psd = torch.from_numpy(Om).to(dev), torch.from_numpy(Ps).to(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)  # warm
+    e0.record()
+    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)
+    e1.record()
+    torch.cuda.synchronize()
+    P = Problem()
+    P.sampler_ms = e0.elapsed_time(e1)
+    tree = hbs.Tree(n, leaf)
+    f = hbs.Factors.create(tree, k, s, args.path)
+    P.rows = n
+    P.compress = lambda: f.compress_into(Omd, Yd, Psd, Zd)
+    P.handle = f
+    P.leaf_sets = [(tree.leaf_sizes(), k, s)]
+    P.config = {"N": n, "k": k, "leaf_max": leaf, "leaf": tree.leaf_sizes()[0], "s": s, "levels": tree.levels,
+                "sampler": args.sampler}
+    G = torch.from_numpy(inputs.probes(rs[inputs.STREAM_PROBES], n, 8)).to(dev)
+
+    def error():
+        AG, _ = hbs.sample_logkernel(xd, yd, G, G)
+        TG = f.apply(G)
+        e = float(torch.linalg.norm(TG - AG) / torch.linalg.norm(AG))
+        ins = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
+        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the black box on 8 Gaussian probes"}
+    P.error = error
+
+    def cpu():
+        from oracle import logkernel as olog
+        from oracle import tree as otree
+        levels = otree.cluster_tree(n, leaf)
+        a, b = levels[args.cpu_subtree_level][0]
+        rows = np.arange(a, b)
+        YZ = olog.sample(x, y, np.hstack((Om, Ps)), rows)  # the oracle's samples of those rows
+        Ysub, Zsub = np.zeros_like(Om), np.zeros_like(Ps)
+        Ysub[a:b], Zsub[a:b] = YZ[:, :s], YZ[:, s:]
+        return cpu_baseline(k, leaf, levels, Om, Ysub, Ps, Zsub, args.cpu_subtree_level, args.workload)
+    P.cpu = cpu
+    return P
+
+
+def _synthetic_instance(hbs, torch, inputs, dev, n, k, leaf, s, rs):
+    """Import a seeded exact-rank generator; samples by the library's Algorithm 1."""
+    tree = hbs.Tree(n, leaf)
+    gen = inputs.synthetic_generators(rs[inputs.STREAM_GENERATOR], tree.leaf_sizes(), k)
+    lv = {}
+    for l in range(1, tree.levels + 1):
+        mm = max(U.shape[0] for U in gen["U"][l])
+        pad = lambda blocks, c: np.stack([np.pad(b_, ((0, mm - b_.shape[0]), (0, c - b_.shape[1]))) for b_ in blocks])
+        lv[l] = {"U": torch.from_numpy(pad(gen["U"][l], k)).to(dev), "V": torch.from_numpy(pad(gen["V"][l], k)).to(dev),
+                 "D": torch.from_numpy(pad(gen["D"][l], mm)).to(dev)}
+    A = hbs.import_factors(tree, k, lv, torch.from_numpy(gen["D0"]).to(dev))
+    del lv
+    Om = torch.from_numpy(inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)).to(dev)
+    Ps = torch.from_numpy(inputs.gaussian(rs[inputs.STREAM_PSI], n, s)).to(dev)
+    Y = A.apply(Om)
+    Z = A.apply(Ps, transpose=True)
+    G = torch.from_numpy(inputs.probes(rs[inputs.STREAM_PROBES], n, 8)).to(dev)
+    return tree, A, Om, Y, Ps, Z, G
+
+
+def setup_synthetic(wl, args, hbs, torch, inputs, dev):
+    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
+    t0 = time.perf_counter()
+    tree, A, Om, Y, Ps, Z, G = _synthetic_instance(hbs, torch, inputs, dev, n, k, leaf, s, inputs.streams(wl["id"]))
+    torch.cuda.synchronize()
+    log(f"generator and samples ready in {time.perf_counter() - t0:.1f} s")
+    P = Problem()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    A.apply(Om)
+    A.apply(Ps, transpose=True)
+    e1.record()
+    torch.cuda.synchronize()
+    P.sampler_ms = e0.elapsed_time(e1)
+    f = hbs.Factors.create(tree, k, s, args.path)
+    P.rows = n
+    P.compress = lambda: f.compress_into(Om, Y, Ps, Z)
+    P.handle = f
+    P.leaf_sets = [(tree.leaf_sizes(), k, s)]
+    P.config = {"N": n, "k": k, "leaf_max": leaf, "leaf": tree.leaf_sizes()[0], "s": s, "levels": tree.levels,
+                "sampler": "Algorithm 1 on the generator"}
+
+    def error():
+        AG = A.apply(G)
+        e = float(torch.linalg.norm(f.apply(G) - AG) / torch.linalg.norm(AG))
+        ins = float(torch.linalg.norm(f.apply(Om) - Y) / torch.linalg.norm(Y))
+        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the exact generator on 8 Gaussian probes"}
+    P.error = error
+
+    def cpu():
+        from oracle import tree as otree
+        levels = otree.cluster_tree(n, leaf)
+        sub = args.cpu_subtree_level + max(0, tree.levels - 10)
+        return cpu_baseline(k, leaf, levels, Om.cpu().numpy(), Y.cpu().numpy(), Ps.cpu().numpy(), Z.cpu().numpy(),
+                            sub, args.workload)
+    P.cpu = cpu
+    return P
+
+
+def setup_batch(wl, args, hbs, torch, inputs, dev):
+    spec = inputs.batch_instances(wl["id"], wl["count"], wl["n_lo"], wl["n_hi"], wl["ks"])
+    t0 = time.perf_counter()
+    inst = []
+    for x in spec:
+        rs = inputs.streams(wl["id"], extra=(x["index"],))
+        inst.append(_synthetic_instance(hbs, torch, inputs, dev, x["n"], x["k"], x["leaf_max"], x["s"], rs))
+    torch.cuda.synchronize()
+    log(f"{len(spec)} generators and samples ready in {time.perf_counter() - t0:.1f} s")
+    trees = [i[0] for i in inst]
+    Om, Y, Ps, Z = ([i[j] for i in inst] for j in (2, 3, 4, 5))
+    b = hbs.Batch(trees, [x["k"] for x in spec], [x["s"] for x in spec], args.path)
+    P = Problem()
+    P.sampler_ms = float("nan")
+    P.rows = sum(x["n"] for x in spec)
+    P.compress = lambda: b.compress(Om, Y, Ps, Z)
+    P.handle = b.factors(0)
+    P.leaf_sets = [(t.leaf_sizes(), x["k"], x["s"]) for t, x in zip(trees, spec)]
+    P.config = {"instances": len(spec), "N_total": P.rows, "N_range": [wl["n_lo"], wl["n_hi"]], "k": list(wl["ks"]),
+                "leaf_max": "2k", "s": "3k + 10", "levels": [min(t.levels for t in trees), max(t.levels for t in trees)]}
+
+    def error():
+        worst = 0.0
+        for i, (tree, A, om, yy, ps, zz, G) in enumerate(inst):
+            AG = A.apply(G)
+            worst = max(worst, float(torch.linalg.norm(b.factors(i).apply(G) - AG) / torch.linalg.norm(AG)))
+        return {"rel_apply_err": worst, "reference": "each instance's exact generator on 8 Gaussian probes (worst)"}
+    P.error = error
+
+    def cpu():
+        from oracle import tree as otree
+        i = max(range(len(spec)), key=lambda j: spec[j]["n"])
+        tree, A, om, yy, ps, zz, G = inst[i]
+        levels = otree.cluster_tree(spec[i]["n"], spec[i]["leaf_max"])
+        out = cpu_baseline(spec[i]["k"], spec[i]["leaf_max"], levels, om.cpu().numpy(), yy.cpu().numpy(),
+                           ps.cpu().numpy(), zz.cpu().numpy(), 2, f"the largest instance ({spec[i]['n']} rows)")
+        return out
+    P.cpu = cpu
+    return P
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -136,9 +285,6 @@ def main():
     from paper_2205_02990_amd import hbs
 
     wl = dict(inputs.WORKLOADS[args.workload])
-    if wl["kind"] != "logkernel":
-        raise SystemExit("bench.py drives the log-kernel workloads")
-    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hbs.load()
@@ -151,44 +297,28 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # ---- inputs (seeded, host) and samples (GPU black box) -----------------
-    rs = inputs.streams(wl["id"])
-    x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
-    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
-    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
-    xd, yd = torch.from_numpy(x).to(dev), torch.from_numpy(y).to(dev)
-    Omd, Psd = torch.from_numpy(Om).to(dev), torch.from_numpy(Ps).to(dev)
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
+    setup = {"logkernel": setup_logkernel, "synthetic": setup_synthetic, "batch": setup_batch}[wl["kind"]]
+    P = setup(wl, args, hbs, torch, inputs, dev)
+    log(f"workload {args.workload}: {P.config}; sampler {P.sampler_ms:.2f} ms; path {args.path}")
+    f = P.handle
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)  # warm
-    e0.record()
-    Yd, Zd = hbs.sample_logkernel(xd, yd, Omd, Psd, precision=args.sampler)
-    e1.record()
-    torch.cuda.synchronize()
-    sampler_ms = e0.elapsed_time(e1)
-    log(f"workload {args.workload}: N={n} k={k} leaf_max={leaf} s={s}; sampler {sampler_ms:.2f} ms")
-
-    tree = hbs.Tree(n, leaf)
-    leaf_sizes = tree.leaf_sizes()
-    f = hbs.Factors.create(tree, k, s, args.path)
 
     # ---- warmup, then K timed sweeps (the captured graph, as callers run it)
     for _ in range(args.warmup):
-        f.compress_into(Omd, Yd, Psd, Zd)
+        P.compress()
     torch.cuda.synchronize()
     f.check()
     t0 = time.perf_counter()
     e0.record()
     for _ in range(args.steps):
-        f.compress_into(Omd, Yd, Psd, Zd)
+        P.compress()
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = e0.elapsed_time(e1)
     f.check()
     ms_per_step = gpu_ms / args.steps
-    rows_per_s = n / (ms_per_step / 1e3)
+    rows_per_s = P.rows / (ms_per_step / 1e3)
     log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms), "
         f"{rows_per_s:.4g} rows/s")
 
@@ -198,7 +328,7 @@ def main():
     f.profile_read()
     e0.record()
     for _ in range(args.steps):
-        f.compress_into(Omd, Yd, Psd, Zd)
+        P.compress()
     e1.record()
     torch.cuda.synchronize()
     traced_ms = e0.elapsed_time(e1) / args.steps
@@ -208,24 +338,23 @@ def main():
     log(f"traced pass {traced_ms:.3f} ms/step; kernel ms/step: " +
         ", ".join(f"{c} {v[0] / args.steps:.3f} ({v[1] // args.steps} launches)" for c, v in prof.items()))
 
-    # ---- accuracy of the result against the black box ------------------------
-    G = torch.from_numpy(inputs.probes(rs[inputs.STREAM_PROBES], n, 8)).to(dev)
-    AG, _ = hbs.sample_logkernel(xd, yd, G, G)
-    TG = f.apply(G)
-    rel_err = float(torch.linalg.norm(TG - AG) / torch.linalg.norm(AG))
-    in_sample = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
-    log(f"relative apply error vs the black box on 8 probes: {rel_err:.3e}; in-sample {in_sample:.3e}")
+    acc = P.error()
+    log(f"accuracy: {acc}")
 
     # ---- roofline of the dominant kernel (the QR kernel, lq_kernel) ----------
-    model = sweep_model(leaf_sizes, k, s)
+    model = {"lq": 0.0, "col": 0.0, "tail": 0.0, "root": 0.0, "lq_bytes": 0.0}
+    for leaf_sizes, k, s in P.leaf_sets:
+        mdl = sweep_model(leaf_sizes, k, s)
+        for c in model:
+            model[c] += mdl[c]
     lq_ms, lq_launches = prof["lq"][0] / args.steps, prof["lq"][1] / args.steps
     avg_launch_ms = lq_ms / lq_launches
-    per_launch = model["lq"] / model["launches"]
+    per_launch = model["lq"] / lq_launches
     achieved = per_launch / (avg_launch_ms / 1e3) / 1e12
     traffic = None
     tfile = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                          f"lq_kernel_{args.workload}_traffic.json")
-    if os.path.exists(tfile):
+    if os.path.exists(tfile) and args.path == "fp64":
         with open(tfile) as fh:
             tr = json.load(fh)
         if tr.get("source_digest") == _side_digest():
@@ -233,24 +362,23 @@ def main():
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP64_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
                 "kernel": "lq_kernel", "flops_per_launch": per_launch, "avg_launch_ms": avg_launch_ms,
-                "algorithmic_hbm_bytes_per_launch": model["lq_bytes"] / model["launches"]}
+                "algorithmic_hbm_bytes_per_launch": model["lq_bytes"] / lq_launches}
     total_flops = sum(model[c] for c in ("lq", "col", "tail", "root"))
 
     out = {
         "metric": METRIC, "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "N": n, "k": k, "leaf_max": leaf, "leaf": leaf_sizes[0], "s": s,
-                   "levels": tree.levels, "path": args.path, "sampler": args.sampler},
+        "vs_baseline": None, "dtype": "f64" if args.path == "fp64" else "f64+i8-slices", "data": "synthetic",
+        "config": {"workload": args.workload, **P.config, "path": args.path},
         "roofline": roofline,
-        "rel_apply_err": rel_err, "in_sample_err": in_sample,
-        "sampler_ms": sampler_ms, "rows_per_s_incl_sampler": n / ((ms_per_step + sampler_ms) / 1e3),
+        **acc,
+        "sampler_ms": P.sampler_ms, "rows_per_s_incl_sampler": P.rows / ((ms_per_step + P.sampler_ms) / 1e3),
         "sweep_tflops_model": total_flops / (ms_per_step / 1e3) / 1e12,
         "traced_ms_per_step": traced_ms,
         "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, x, y, Om, Ps, args.cpu_subtree_level)
+        out["cpu_baseline"] = P.cpu()
         log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} rows/s on {out['cpu_baseline']['cores']} threads")
     print(json.dumps(out), flush=True)
 
