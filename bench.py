@@ -113,6 +113,12 @@ class Problem:
     pass
 
 
+def _power_starts(inputs, wid, n, torch, dev):
+    """Seeded starting vectors of the two power iterations (error, norm)."""
+    rs = inputs.streams(wid, 2, extra=(0x50,))
+    return tuple(torch.from_numpy(inputs.gaussian(r, n, 1)[:, 0].copy()).to(dev) for r in rs)
+
+
 def setup_logkernel(wl, args, hbs, torch, inputs, dev):
     n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
     rs = inputs.streams(wl["id"])
@@ -144,7 +150,10 @@ def setup_logkernel(wl, args, hbs, torch, inputs, dev):
         TG = f.apply(G)
         e = float(torch.linalg.norm(TG - AG) / torch.linalg.norm(AG))
         ins = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
-        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the black box on 8 Gaussian probes"}
+        pw = hbs.power_rel_error(f, hbs.LogKernelBox(xd, yd), *_power_starts(inputs, wl["id"], n, torch, dev))
+        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the black box on 8 Gaussian probes",
+                "power_rel_err": pw, "power_reference": "||A~ - A|| / ||A||, 20 power steps each (section 5)",
+                "floats_per_dof": f.floats_per_dof()}
     P.error = error
 
     def cpu():
@@ -207,7 +216,10 @@ def setup_synthetic(wl, args, hbs, torch, inputs, dev):
         AG = A.apply(G)
         e = float(torch.linalg.norm(f.apply(G) - AG) / torch.linalg.norm(AG))
         ins = float(torch.linalg.norm(f.apply(Om) - Y) / torch.linalg.norm(Y))
-        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the exact generator on 8 Gaussian probes"}
+        pw = hbs.power_rel_error(f, A, *_power_starts(inputs, wl["id"], n, torch, dev))
+        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the exact generator on 8 Gaussian probes",
+                "power_rel_err": pw, "power_reference": "||A~ - A|| / ||A||, 20 power steps each (section 5)",
+                "floats_per_dof": f.floats_per_dof()}
     P.error = error
 
     def cpu():
@@ -246,7 +258,13 @@ def setup_batch(wl, args, hbs, torch, inputs, dev):
         for i, (tree, A, om, yy, ps, zz, G) in enumerate(inst):
             AG = A.apply(G)
             worst = max(worst, float(torch.linalg.norm(b.factors(i).apply(G) - AG) / torch.linalg.norm(AG)))
-        return {"rel_apply_err": worst, "reference": "each instance's exact generator on 8 Gaussian probes (worst)"}
+        i = max(range(len(spec)), key=lambda j: spec[j]["n"])
+        fi = b.factors(i)
+        pw = hbs.power_rel_error(fi, inst[i][1], *_power_starts(inputs, wl["id"], spec[i]["n"], torch, dev))
+        return {"rel_apply_err": worst, "reference": "each instance's exact generator on 8 Gaussian probes (worst)",
+                "power_rel_err": pw, "power_reference": (f"||A~ - A|| / ||A||, 20 power steps each (section 5), "
+                                                         f"largest instance ({spec[i]['n']} rows)"),
+                "floats_per_dof": sum(b.factors(j).floats_per_dof() * spec[j]["n"] for j in range(len(spec))) / P.rows}
     P.error = error
 
     def cpu():

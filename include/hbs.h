@@ -193,6 +193,43 @@ hbs_status hbs_profile(hbs_factors* f, int enable);
  * memory) accumulated since the previous read, and reset them. */
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass);
 
+/* Storage of the factors (quantity (4) of section 5): the number of FP64
+ * values of every U_tau, V_tau (m_tau x k), D_tau (m_tau x m_tau) and of
+ * D^(0), each counted at its own size (no padding), divided by N.  Host
+ * arithmetic only; enqueues nothing. */
+hbs_status hbs_floats_per_dof(const hbs_factors* f, double* out);
+
+/* A black box for the accuracy estimate: y = B x (transpose = 0) or
+ * y = B^* x (transpose != 0) for one device vector x of length n, enqueued on
+ * hip_stream.  ctx is passed through unchanged. */
+typedef hbs_status (*hbs_matvec)(void* ctx, int32_t transpose, const double* x, double* y, void* hip_stream);
+
+/* Section 5's operator-norm estimate by power iteration: with
+ * E = A~ - B (f and black_box both given), A~ (black_box NULL) or B (f NULL),
+ *   v_i = E^* E (v_{i-1} / ||v_{i-1}||), i = 1 .. steps,
+ * starting from the device vector v0 (length n, read only), writes
+ * sqrt(||v_steps||) to *out (host).  The paper's relative error is
+ * hbs_power_norm(f, B) / hbs_power_norm(NULL, B), 20 steps each.  f's N must
+ * equal n.  Allocates 4 n + 257 doubles of device workspace for the call and
+ * waits for the stream before returning.  HBS_EINVAL if both f and
+ * black_box are NULL, n < 1, steps < 1 or a pointer is NULL; a status
+ * returned by black_box is passed on. */
+hbs_status hbs_power_norm(hbs_factors* f, hbs_matvec black_box, void* ctx, int64_t n, const double* v0,
+                          int32_t steps, double* out, void* hip_stream);
+
+/* hbs_matvec over a factor set: ctx is an hbs_factors*; y = A~ x or A~^* x. */
+hbs_status hbs_matvec_factors(void* ctx, int32_t transpose, const double* x, double* y, void* hip_stream);
+
+/* hbs_matvec of the log-kernel black box below, one vector at a time (the
+ * kernel is symmetric, so transpose is ignored).  ctx is a HOST pointer to
+ * this struct, whose x and y are the device point coordinates. */
+typedef struct {
+  int64_t n;
+  const double* x;
+  const double* y;
+} hbs_logkernel_points;
+hbs_status hbs_matvec_logkernel(void* ctx, int32_t transpose, const double* x, double* y, void* hip_stream);
+
 /* Stand-in black box: the log kernel A(i, j) = log|x_i - x_j| (i != j),
  * A(i, i) = 0, on points (x[i], y[i]) (device arrays of n FP64 values).
  * Writes Y = A Omega and Z = A^* Psi = A Psi (A is symmetric); Omega, Psi, Y,

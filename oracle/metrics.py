@@ -14,11 +14,15 @@ def probe_rel_error(ref_apply, test_apply, G=None):
     return float(np.linalg.norm(T - R) / np.linalg.norm(R))
 
 
-def power_norm(matvec, rmatvec, n, steps=20, rng=None):
-    """Operator 2-norm estimate of section 5: start from a random v_0 and take
-    v_i = B^* B (v_{i-1} / ||v_{i-1}||), i = 1..steps; return sqrt(||v_steps||)."""
-    rng = np.random.default_rng(0) if rng is None else rng
-    v = rng.standard_normal(n)
+def power_norm(matvec, rmatvec, n, steps=20, rng=None, v0=None):
+    """Operator 2-norm estimate of section 5: start from a random v_0 (or the
+    given one) and take v_i = B^* B (v_{i-1} / ||v_{i-1}||), i = 1..steps;
+    return sqrt(||v_steps||)."""
+    if v0 is None:
+        rng = np.random.default_rng(0) if rng is None else rng
+        v = rng.standard_normal(n)
+    else:
+        v = np.array(v0, dtype=np.float64).reshape(n)
     for _ in range(steps):
         v = rmatvec(matvec(v / np.linalg.norm(v)))
     return float(np.sqrt(np.linalg.norm(v)))

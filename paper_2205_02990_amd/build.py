@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(HERE, "libhbs.so")
-SOURCES = ["hbs_side.hip", "hbs_dense.hip", "hbs_tail.hip", "hbs_logkernel.hip", "hbs_host.hip"]
+SOURCES = ["hbs_side.hip", "hbs_dense.hip", "hbs_tail.hip", "hbs_logkernel.hip", "hbs_metrics.hip", "hbs_host.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

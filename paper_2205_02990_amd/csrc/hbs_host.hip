@@ -441,6 +441,10 @@ Instance& inst_of(const hbs_factors* f) { return f->b->inst[f->idx]; }
 
 }  // namespace
 
+namespace hbs {
+int64_t factors_n(const hbs_factors* f) { return inst_of(f).tree.n; }
+}  // namespace hbs
+
 extern "C" {
 
 const char* hbs_status_str(hbs_status s) {
@@ -741,6 +745,22 @@ hbs_status hbs_root(const hbs_factors* f, const double** D0, int32_t* rows) {
   const Instance& in = inst_of(f);
   *D0 = in.D0;
   *rows = in.n0;
+  return HBS_OK;
+}
+
+hbs_status hbs_floats_per_dof(const hbs_factors* f, double* out) {
+  if (!f || !out) return HBS_EINVAL;
+  const Instance& in = inst_of(f);
+  const hbs_tree& t = in.tree;
+  const int64_t k = in.k;
+  double total = (double)in.n0 * in.n0;  // D^(0)
+  for (int l = 1; l <= in.L; ++l) {
+    for (int64_t i = 0; i < ((int64_t)1 << l); ++i) {
+      const int64_t m = (l == in.L) ? t.start[l][i + 1] - t.start[l][i] : 2 * k;
+      total += (double)(2 * m * k + m * m);  // U_tau, V_tau, D_tau
+    }
+  }
+  *out = total / (double)t.n;
   return HBS_OK;
 }
 

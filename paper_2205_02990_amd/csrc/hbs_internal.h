@@ -68,6 +68,8 @@ hipError_t prepare_side_kernels();
 // QR of the test blocks, reflectors applied to the samples, Y Omega^dagger
 // (both sides of every box; the root's one side)
 hipError_t launch_lq(const SweepArgs& a, hipStream_t st);
+// N of a factor set's tree (host)
+int64_t factors_n(const hbs_factors* f);
 // truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
 hipError_t launch_col(const SweepArgs& a, hipStream_t st);
 // the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c)

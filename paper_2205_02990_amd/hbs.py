@@ -72,6 +72,8 @@ def load():
         "hbs_compress_batched": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(I32),
                                        ctypes.POINTER(P), ctypes.POINTER(P), ctypes.POINTER(P),
                                        ctypes.POINTER(P), ctypes.POINTER(I64), I32, VP, ctypes.POINTER(P)]),
+        "hbs_floats_per_dof": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
+        "hbs_power_norm": (I32, [P, VP, VP, I64, VP, I32, ctypes.POINTER(ctypes.c_double), VP]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -210,6 +212,15 @@ class Factors:
                 "V": _copy_out(v.V, (v.nodes, v.m, v.k), stream),
                 "D": _copy_out(v.D, (v.nodes, v.m, v.m), stream)}
 
+    def floats_per_dof(self) -> float:
+        """Stored FP64 values per degree of freedom (quantity (4) of section 5)."""
+        out = ctypes.c_double()
+        _check(load().hbs_floats_per_dof(self._h, ctypes.byref(out)), "hbs_floats_per_dof")
+        return out.value
+
+    def _matvec(self):
+        return ctypes.cast(load().hbs_matvec_factors, ctypes.c_void_p), self._h
+
     def root(self, stream=None) -> torch.Tensor:
         p, n = ctypes.c_void_p(), ctypes.c_int32()
         _check(load().hbs_root(self._h, ctypes.byref(p), ctypes.byref(n)), "hbs_root")
@@ -340,3 +351,43 @@ def sample_logkernel(x: torch.Tensor, y: torch.Tensor, Om: torch.Tensor, Ps: tor
                                        _dev_f64(Z, "Z"), s, Om.stride(0), PRECISION[precision], _stream(stream)),
            "hbs_sample_logkernel")
     return Y, Z
+
+
+class LogKernelPoints(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+
+
+class LogKernelBox:
+    """The log-kernel black box (hbs_matvec_logkernel) on device point
+    coordinates x, y (1-D float64 GPU tensors)."""
+
+    def __init__(self, x: torch.Tensor, y: torch.Tensor):
+        if not (x.is_cuda and y.is_cuda and x.dtype == y.dtype == torch.float64 and x.dim() == y.dim() == 1
+                and x.shape == y.shape and x.is_contiguous() and y.is_contiguous()):
+            raise ValueError("x, y must be contiguous 1-D float64 GPU tensors of one length")
+        self.x, self.y = x, y
+        self.pts = LogKernelPoints(x.shape[0], x.data_ptr(), y.data_ptr())
+
+    def _matvec(self):
+        return ctypes.cast(load().hbs_matvec_logkernel, ctypes.c_void_p), ctypes.cast(ctypes.pointer(self.pts),
+                                                                                    ctypes.c_void_p)
+
+
+def power_norm(factors: Factors | None, black_box, v0: torch.Tensor, steps: int = 20, stream=None) -> float:
+    """Section 5's power-iteration estimate of ||A~ - B||_2 (hbs_power_norm);
+    either operand may be None.  ``black_box`` is a Factors or LogKernelBox."""
+    if not (v0.is_cuda and v0.dtype == torch.float64 and v0.dim() == 1 and v0.is_contiguous()):
+        raise ValueError("v0 must be a contiguous 1-D float64 GPU tensor")
+    fn, ctx = black_box._matvec() if black_box is not None else (None, None)
+    out = ctypes.c_double()
+    _check(load().hbs_power_norm(factors._h if factors is not None else None, fn, ctx, v0.shape[0],
+                                 ctypes.c_void_p(v0.data_ptr()), int(steps), ctypes.byref(out), _stream(stream)),
+           "hbs_power_norm")
+    return out.value
+
+
+def power_rel_error(factors: Factors, black_box, v0_err: torch.Tensor, v0_norm: torch.Tensor,
+                    steps: int = 20, stream=None) -> float:
+    """||A~ - B|| / ||B||, both by power_norm (section 5's accuracy measure)."""
+    return power_norm(factors, black_box, v0_err, steps, stream) / power_norm(None, black_box, v0_norm, steps,
+                                                                               stream)

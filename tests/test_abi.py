@@ -24,6 +24,7 @@ def _lib():
 def declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"typedef[^;]*;", "", text)  # function-pointer types are not symbols
     return sorted(set(re.findall(r"\b(hbs_[a-z_0-9]+)\s*\(", text)))
 
 

@@ -1,0 +1,153 @@
+"""GPU parity of section 5's reported quantities: the power-iteration
+estimate of ||A~ - A|| / ||A|| (hbs_power_norm, with the factor-set and the
+log-kernel black boxes) and the storage in floats per degree of freedom.
+
+Every expected value comes from the oracle on the same seeded inputs:
+floats/DOF is an exact count (compared for equality); the log-kernel matvec
+is a plain product (1e-13); the power estimate follows the same iteration
+from the same v_0, so the two differ by rounding only (1e-11 where the
+estimated operator's norm is O(1); for the compression error itself, whose
+operator is the difference of two nearly equal operators, 1e-4 relative).
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import inputs  # noqa: E402
+from oracle import hbs as ohbs  # noqa: E402
+from oracle import logkernel as olog  # noqa: E402
+from oracle import metrics as omet  # noqa: E402
+from oracle import tree as otree  # noqa: E402
+from tests.helpers import rel, synthetic_case  # noqa: E402
+from tests.test_gpu_parity import dev, gpu_compress, host, import_generator  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hbs():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2205_02990_amd import hbs as h
+    h.load()
+    return h
+
+
+def start_vectors(n, seed):
+    rs = inputs.streams(7, 2, extra=(n, seed))
+    return inputs.gaussian(rs[0], n, 1)[:, 0], inputs.gaussian(rs[1], n, 1)[:, 0]
+
+
+@pytest.mark.parametrize("n,k,leaf,s", [(1024, 16, 32, 58), (1000, 12, 24, 46), (20, 8, 32, 30)])
+def test_floats_per_dof_matches_oracle(hbs, n, k, leaf, s):
+    c = synthetic_case(n, k, leaf, s)
+    tree, f = gpu_compress(hbs, c, leaf)
+    orc = ohbs.compress(c["levels"], k, c["Om"], c["Y"], c["Ps"], c["Z"])
+    print(f"[metrics] floats/DOF n={n} k={k}: {f.floats_per_dof():.6f}", flush=True)
+    assert f.floats_per_dof() == ohbs.floats_per_dof(orc)
+    assert import_generator(hbs, tree, c).floats_per_dof() == ohbs.floats_per_dof(c["gen"])
+
+
+def test_logkernel_matvec_matches_oracle(hbs):
+    """hbs_matvec_logkernel through the C ABI against the oracle's dense rows."""
+    n = 1500
+    x, y = inputs.ellipse_points(n)
+    v = inputs.gaussian(inputs.streams(7, 1, extra=(n,))[0], n, 1)
+    box = hbs.LogKernelBox(dev(x), dev(y))
+    vin = dev(v[:, 0])
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    fn = hbs.load().hbs_matvec_logkernel
+    fn.restype = ctypes.c_int32
+    fn.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    for tr in (0, 1):
+        st = fn(ctypes.cast(ctypes.pointer(box.pts), ctypes.c_void_p), tr, vin.data_ptr(), out.data_ptr(),
+                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert st == 0
+        ref = olog.sample(x, y, v)[:, 0]
+        e = rel(host(out), ref)
+        print(f"[metrics] log-kernel matvec n={n} transpose={tr}: {e:.2e}", flush=True)
+        assert e <= 1e-13
+
+
+def test_power_norm_of_a_factor_set_matches_oracle(hbs):
+    """||A||_2 of a synthetic HBS matrix by 20 power steps, E = A~ alone and
+    E = B alone (the same generator as a black box): both equal the oracle's
+    iteration from the same v_0, and agree with the dense 2-norm."""
+    c = synthetic_case(256, 8, 16, 30)
+    tree = hbs.Tree(256, 16)
+    g = import_generator(hbs, tree, c)
+    v0, _ = start_vectors(256, 1)
+    ref = omet.power_norm(lambda v: ohbs.apply(c["gen"], v[:, None])[:, 0],
+                          lambda v: ohbs.apply(c["gen"], v[:, None], transpose=True)[:, 0], 256, 20, v0=v0)
+    a = hbs.power_norm(g, None, dev(v0))
+    b = hbs.power_norm(None, g, dev(v0))
+    dense = np.linalg.norm(ohbs.dense(c["gen"]), 2)
+    print(f"[metrics] power norm: gpu {a:.15e} / {b:.15e}, oracle {ref:.15e}, dense {dense:.15e}", flush=True)
+    assert abs(a - ref) <= 1e-11 * ref and abs(b - ref) <= 1e-11 * ref
+    assert abs(ref - dense) <= 1e-2 * dense  # 20 steps leave this matrix's estimate 0.2 % low
+
+
+def test_power_norm_of_a_difference_matches_oracle(hbs):
+    """E = A~_1 - A_2 for two different matrices on one tree (a compression of
+    generator 1 against generator 2 as the black box): a well-separated
+    difference, estimated alike on both sides."""
+    c1 = synthetic_case(512, 8, 16, 30, extra=(1,))
+    c2 = synthetic_case(512, 8, 16, 30, extra=(2,))
+    tree, f1 = gpu_compress(hbs, c1, 16)
+    g2 = import_generator(hbs, tree, c2)
+    v0, _ = start_vectors(512, 2)
+    o1 = ohbs.compress(c1["levels"], 8, c1["Om"], c1["Y"], c1["Ps"], c1["Z"])
+
+    def mv(v, t=False):
+        return ohbs.apply(o1, v[:, None], transpose=t)[:, 0] - ohbs.apply(c2["gen"], v[:, None], transpose=t)[:, 0]
+
+    ref = omet.power_norm(mv, lambda v: mv(v, True), 512, 20, v0=v0)
+    got = hbs.power_norm(f1, g2, dev(v0))
+    print(f"[metrics] ||A1~ - A2||: gpu {got:.15e}, oracle {ref:.15e}", flush=True)
+    assert abs(got - ref) <= 1e-11 * ref
+
+
+def test_power_rel_error_exact_rank(hbs):
+    """Exact-rank input: the compression reproduces A, so the paper's error
+    measure sits at rounding level."""
+    c = synthetic_case(1024, 16, 32, 58)
+    tree, f = gpu_compress(hbs, c, 32)
+    g = import_generator(hbs, tree, c)
+    v0, v1 = start_vectors(1024, 3)
+    e = hbs.power_rel_error(f, g, dev(v0), dev(v1))
+    print(f"[metrics] exact rank: power relative error {e:.2e}", flush=True)
+    assert e <= 1e-12
+
+
+def test_power_rel_error_logkernel_matches_oracle(hbs):
+    """Log kernel (section 5.1's setting, ellipse points, N = 2048, k = 16,
+    s = 58): the GPU estimate of ||A~ - A|| / ||A|| with the GPU log-kernel
+    black box equals the oracle's estimate with its own compression and dense
+    kernel, to the precision that separates the two compressions."""
+    n, k, leaf, s = 2048, 16, 32, 58
+    x, y = inputs.ellipse_points(n)
+    rs = inputs.streams(8, extra=(n, k))
+    Om, Ps = inputs.gaussian(rs[1], n, s), inputs.gaussian(rs[2], n, s)
+    Y = olog.sample(x, y, Om)
+    Z = olog.sample(x, y, Ps)
+    levels = otree.cluster_tree(n, leaf)
+    orc = ohbs.compress(levels, k, Om, Y, Ps, Z)
+    tree = hbs.Tree(n, leaf)
+    f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z))
+    f.check()
+    v0, v1 = start_vectors(n, 4)
+    box = hbs.LogKernelBox(dev(x), dev(y))
+    got = hbs.power_rel_error(f, box, dev(v0), dev(v1))
+
+    def akv(v):
+        return olog.sample(x, y, v[:, None])[:, 0]
+
+    num = omet.power_norm(lambda v: ohbs.apply(orc, v[:, None])[:, 0] - akv(v),
+                          lambda v: ohbs.apply(orc, v[:, None], transpose=True)[:, 0] - akv(v), n, 20, v0=v0)
+    den = omet.power_norm(akv, akv, n, 20, v0=v1)
+    ref = num / den
+    print(f"[metrics] log kernel N={n} k={k}: power relative error gpu {got:.6e}, oracle {ref:.6e}", flush=True)
+    assert abs(got - ref) <= 1e-4 * ref
