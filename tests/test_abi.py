@@ -83,3 +83,26 @@ def test_factor_creation_validates_before_device_work(n, leaf, k, s, status):
     with pytest.raises(hbs.HBSError) as e:
         hbs.Factors.create(t, k, s)
     assert e.value.status == getattr(hbs, "HBS_" + status)
+
+
+def test_reporting_entry_points_validate_before_device_work():
+    """hbs_power_norm and hbs_floats_per_dof reject bad arguments synchronously
+    (no operator, no start vector, no steps, NULL outputs)."""
+    hbs = _lib()
+    lib = hbs.load()
+    out = ctypes.c_double()
+    dummy = ctypes.c_void_p(8)  # never dereferenced: every call below fails its argument checks first
+    fn = ctypes.cast(lib.hbs_matvec_factors, ctypes.c_void_p)
+    assert lib.hbs_power_norm(None, None, None, 16, dummy, 20, ctypes.byref(out), None) == hbs.HBS_EINVAL
+    assert lib.hbs_power_norm(None, fn, None, 0, dummy, 20, ctypes.byref(out), None) == hbs.HBS_EINVAL
+    assert lib.hbs_power_norm(None, fn, None, 16, None, 20, ctypes.byref(out), None) == hbs.HBS_EINVAL
+    assert lib.hbs_power_norm(None, fn, None, 16, dummy, 0, ctypes.byref(out), None) == hbs.HBS_EINVAL
+    assert lib.hbs_power_norm(None, fn, None, 16, dummy, 20, None, None) == hbs.HBS_EINVAL
+    assert lib.hbs_floats_per_dof(None, ctypes.byref(out)) == hbs.HBS_EINVAL
+    lib.hbs_matvec_logkernel.restype = ctypes.c_int32
+    lib.hbs_matvec_logkernel.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]
+    assert lib.hbs_matvec_logkernel(None, 0, dummy, dummy, None) == hbs.HBS_EINVAL
+    pts = hbs.LogKernelPoints(0, 8, 8)
+    assert lib.hbs_matvec_logkernel(ctypes.cast(ctypes.pointer(pts), ctypes.c_void_p), 0, dummy, dummy,
+                                    None) == hbs.HBS_EINVAL
