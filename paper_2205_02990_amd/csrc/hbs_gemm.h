@@ -185,30 +185,26 @@ __device__ __forceinline__ void slice4(const double (&x)[4], int e, int32_t (&w)
   }
 }
 
-// Slice contracted indices [k0 + kSlicePer g, k0 + kSlicePer (g + 1)) of column
-// c0 + c of a row-major operand X (K x ncol, row stride ldx) into
+// Slice this thread's kSlicePer contracted indices [kSlicePer g, kSlicePer (g + 1))
+// of one chunk of column c (values already in registers) into
 // dst[p][c][words of those indices].
 template <int S>
-__device__ __forceinline__ void slice_stage(const double* __restrict__ X, int64_t ldx, int c0, int ncol, int K, int k0, int c,
-                                   int g, int e, int32_t (*dst)[64][kSliceRow]) {
-  const bool okc = c0 + c < ncol;
+__device__ __forceinline__ void slice_regs(const double (&x)[kSlicePer], int c, int g, int e,
+                                           int32_t (*dst)[64][kSliceRow]) {
 #pragma unroll
   for (int w = 0; w < kSlicePer / 4; ++w) {
-    double x[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = k0 + kSlicePer * g + 4 * w + u;
-      const bool ok = okc && kk < K;
-      const double v = X[ok ? kk * ldx + c0 + c : 0];
-      x[u] = ok ? v : 0.0;
-    }
+    const double x4[4] = {x[4 * w], x[4 * w + 1], x[4 * w + 2], x[4 * w + 3]};
     int32_t sw[S];
-    slice4<S>(x, e, sw);
+    slice4<S>(x4, e, sw);
     const int word = slice_word(c, (kSlicePer / 4) * g + w);
 #pragma unroll
     for (int p = 0; p < S; ++p) dst[p][c][word] = sw[p];
   }
 }
+
+// Contracted lengths covered: the products here contract over the rows of one
+// box (K = m_tau <= 128), two chunks of kSliceK.
+constexpr int kSliceChunks = 2;
 
 template <int S>
 __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, const double* __restrict__ L, int64_t ldl,
@@ -220,16 +216,27 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
   const int c = tid & 63, g = tid >> 6;  // staging: output index c, contracted group g
   for (int i0 = 0; i0 < M; i0 += 64) {
     for (int j0 = 0; j0 < N; j0 += 64) {
-      // scales: largest magnitude of each row of L^T and each column of R
-      {
-        const bool oki = i0 + c < M, okj = j0 + c < N;
-        double ma = 0.0, mb = 0.0;
-        for (int kk = g; kk < K; kk += kSliceGroups) {
-          const double va = L[oki ? kk * ldl + i0 + c : 0];
-          const double vb = R[okj ? kk * ldr + j0 + c : 0];
-          ma = fmax(ma, oki ? fabs(va) : 0.0);
-          mb = fmax(mb, okj ? fabs(vb) : 0.0);
+      // this thread's operand values (column c of the L and R tiles, its
+      // contracted indices of every chunk), all loads in flight together; the
+      // scales (largest magnitude of each row of L^T and each column of R)
+      // come from the same registers
+      const bool oki = i0 + c < M, okj = j0 + c < N;
+      double xa[kSliceChunks][kSlicePer], xb[kSliceChunks][kSlicePer];
+      double ma = 0.0, mb = 0.0;
+#pragma unroll
+      for (int h = 0; h < kSliceChunks; ++h)
+#pragma unroll
+        for (int u = 0; u < kSlicePer; ++u) {
+          const int kk = kSliceK * h + kSlicePer * g + u;
+          const bool oka = oki && kk < K, okb = okj && kk < K;
+          const double va = L[oka ? kk * ldl + i0 + c : 0];
+          const double vb = R[okb ? kk * ldr + j0 + c : 0];
+          xa[h][u] = oka ? va : 0.0;
+          xb[h][u] = okb ? vb : 0.0;
+          ma = fmax(ma, fabs(xa[h][u]));
+          mb = fmax(mb, fabs(xb[h][u]));
         }
+      {
         sm.u.red[0][g][c] = ma;
         sm.u.red[1][g][c] = mb;
         __syncthreads();
@@ -249,9 +256,11 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int d = 0; d < S; ++d) acc[b][d] = gemm_i4{0, 0, 0, 0};
-      for (int k0 = 0; k0 < K; k0 += kSliceK) {
-        slice_stage<S>(L, ldl, i0, M, K, k0, c, g, sm.ea[c], sm.u.q.As);
-        slice_stage<S>(R, ldr, j0, N, K, k0, c, g, sm.eb[c], sm.u.q.Bs);
+#pragma unroll
+      for (int h = 0; h < kSliceChunks; ++h) {
+        if (kSliceK * h >= K) break;
+        slice_regs<S>(xa[h], c, g, sm.ea[c], sm.u.q.As);
+        slice_regs<S>(xb[h], c, g, sm.eb[c], sm.u.q.Bs);
         __syncthreads();
         gemm_i4 ap[S];
         const int wa = slice_word(rb + li, 4 * lk);

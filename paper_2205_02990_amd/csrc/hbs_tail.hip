@@ -180,6 +180,7 @@ size_t tail_workspace(int dld, int k) {
 
 hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
+  if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
   if (part == 0) {
     const dim3 grid(a.nboxes, 3 * mt + 4 * sct);
     if (a.mixed)
