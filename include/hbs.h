@@ -208,7 +208,8 @@ typedef hbs_status (*hbs_matvec)(void* ctx, int32_t transpose, const double* x, 
  * E = A~ - B (f and black_box both given), A~ (black_box NULL) or B (f NULL),
  *   v_i = E^* E (v_{i-1} / ||v_{i-1}||), i = 1 .. steps,
  * starting from the device vector v0 (length n, read only), writes
- * sqrt(||v_steps||) to *out (host).  The paper's relative error is
+ * sqrt(||v_steps||) to *out (host); an iterate that vanishes (E = 0 on it)
+ * stays 0, so *out is 0.  The paper's relative error is
  * hbs_power_norm(f, B) / hbs_power_norm(NULL, B), 20 steps each.  f's N must
  * equal n.  Allocates 4 n + 257 doubles of device workspace for the call and
  * waits for the stream before returning.  HBS_EINVAL if both f and

@@ -24,7 +24,10 @@ def power_norm(matvec, rmatvec, n, steps=20, rng=None, v0=None):
     else:
         v = np.array(v0, dtype=np.float64).reshape(n)
     for _ in range(steps):
-        v = rmatvec(matvec(v / np.linalg.norm(v)))
+        nv = np.linalg.norm(v)
+        if nv == 0.0:  # B v_{i-1} = 0: the iteration has stopped at the zero vector
+            return 0.0
+        v = rmatvec(matvec(v / nv))
     return float(np.sqrt(np.linalg.norm(v)))
 
 

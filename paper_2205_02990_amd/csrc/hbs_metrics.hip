@@ -49,12 +49,14 @@ __device__ double sum_parts(const double* __restrict__ part, double* red) {
   return t;
 }
 
-// x = v / ||v||, ||v||^2 being the sum of part[0 .. kRedBlocks - 1].
+// x = v / ||v||, ||v||^2 being the sum of part[0 .. kRedBlocks - 1]; x = 0
+// when v = 0 (E v_{i-1} vanished: the estimate is then 0).
 __global__ void __launch_bounds__(kRedThreads) scale_unit(const double* __restrict__ v,
                                                          const double* __restrict__ part, int64_t n,
                                                          double* __restrict__ x) {
   __shared__ double red[kRedThreads];
-  const double inv = 1.0 / sqrt(sum_parts(part, red));
+  const double ss = sum_parts(part, red);
+  const double inv = ss > 0.0 ? 1.0 / sqrt(ss) : 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kRedThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRedThreads)
     x[i] = v[i] * inv;
 }

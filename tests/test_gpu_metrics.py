@@ -110,6 +110,20 @@ def test_power_norm_of_a_difference_matches_oracle(hbs):
     assert abs(got - ref) <= 1e-11 * ref
 
 
+def test_power_norm_of_zero_difference(hbs):
+    """E = A~ - A~ (a factor set against itself) vanishes after the first
+    step: the estimate is 0, as the oracle's."""
+    c = synthetic_case(256, 8, 16, 30)
+    tree = hbs.Tree(256, 16)
+    g = import_generator(hbs, tree, c)
+    v0, _ = start_vectors(256, 5)
+    gen = lambda v, t=False: ohbs.apply(c["gen"], v[:, None], transpose=t)[:, 0]  # noqa: E731
+    ref = omet.power_norm(lambda v: gen(v) - gen(v), lambda v: gen(v, True) - gen(v, True), 256, 20, v0=v0)
+    got = hbs.power_norm(g, g, dev(v0))
+    print(f"[metrics] ||A - A||: gpu {got}, oracle {ref}", flush=True)
+    assert got == 0.0 and ref == 0.0
+
+
 def test_power_rel_error_exact_rank(hbs):
     """Exact-rank input: the compression reproduces A, so the paper's error
     measure sits at rounding level."""

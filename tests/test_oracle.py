@@ -380,6 +380,17 @@ def test_power_norm_estimate():
     B = Q1 @ np.diag(sv) @ Q2.T
     est = metrics.power_norm(lambda v: B @ v, lambda v: B.T @ v, 60)
     assert est == pytest.approx(np.linalg.norm(B, 2), rel=1e-12)
+    # a given start vector takes the same iteration
+    v0 = np.random.default_rng(0).standard_normal(60)
+    assert metrics.power_norm(lambda v: B @ v, lambda v: B.T @ v, 60, v0=v0) == est
+    # the zero operator, and a start vector in the nullspace, give 0
+    Z = np.zeros((60, 60))
+    assert metrics.power_norm(lambda v: Z @ v, lambda v: Z.T @ v, 60) == 0.0
+    P = np.eye(60)
+    P[0, 0] = 0.0
+    e0 = np.zeros(60)
+    e0[0] = 1.0
+    assert metrics.power_norm(lambda v: P @ v, lambda v: P @ v, 60, v0=e0) == 0.0
 
 
 def test_logkernel_compression_accuracy():
