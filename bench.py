@@ -358,6 +358,13 @@ def main():
 
     acc = P.error()
     log(f"accuracy: {acc}")
+    plan = f.plan()
+    tiles = [f"step {p['step']}: {p['boxes']} boxes m<={p['mmax']} lq {p['lq']['threads']}t/{p['lq']['lanes_per_row']}l "
+             f"{p['lq']['test_slots']}x{p['lq']['sample_slots']}x{p['lq']['col_slots']} chunks {p['lq']['chunks']}"
+             + ("" if p["root"] else f", col {p['col']['threads']}t/{p['col']['lanes_per_row']}l "
+                f"{p['col']['row_slots']}x{p['col']['col_slots']}, tail_b {p['tail_b']}")
+             for p in plan]
+    log(("autotuned" if plan and plan[0]["tuned"] else "heuristic") + " tiles:\n  " + "\n  ".join(tiles))
 
     # ---- roofline of the dominant kernel (the QR kernel, lq_kernel) ----------
     model = {"lq": 0.0, "col": 0.0, "tail": 0.0, "root": 0.0, "lq_bytes": 0.0}
@@ -394,6 +401,7 @@ def main():
         "sweep_tflops_model": total_flops / (ms_per_step / 1e3) / 1e12,
         "traced_ms_per_step": traced_ms,
         "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
+        "tiles": {"autotuned": bool(plan and plan[0]["tuned"]), "steps": tiles},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = P.cpu()

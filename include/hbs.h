@@ -107,7 +107,8 @@ void       hbs_factors_destroy(hbs_factors* f);
  * u_tau_formula, v_tau_formula); D_tau by eq. d_tau_formula; then the
  * reduced test and sample matrices of eq. omega_tau_and_y_tau feed the next
  * level up; the root block is D^(0) = Y_root Omega_root^dagger.  The previous
- * contents of `f` are overwritten. */
+ * contents of `f` are overwritten.  The first call on a factor set also
+ * autotunes the tiles (see hbs_sweep_plan) and waits for the stream. */
 hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* Y, const double* Psi,
                              const double* Z, int64_t ld, void* hip_stream);
 
@@ -192,6 +193,27 @@ hbs_status hbs_profile(hbs_factors* f, int enable);
  * the launch count of each class (arrays of nclass <= 6 entries, host
  * memory) accumulated since the previous read, and reset them. */
 hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32_t nclass);
+
+/* The tile plan of the sweep that computes a factor set (the whole batch's
+ * sweep for a batch handle): one row of HBS_PLAN_COLS int32 per launch step,
+ * written to the host array rows[max_rows][HBS_PLAN_COLS]; *nrows receives the
+ * number of steps (rows beyond max_rows are not written).  Columns: step,
+ * boxes, largest box rows, s, k, root step (0/1), tuned (1 once the
+ * autotuner has chosen; until then the built-in heuristic's choice is
+ * shown), QR tile (threads, lanes per row, test-row slots, sample-row slots,
+ * column slots, sample-row chunks per box), pivoted-QR tile (threads, lanes
+ * per row, sketch-row slots, column slots), tail_b variant (0 one
+ * workgroup per chain, 1 row blocks in parallel).
+ *
+ * Autotuning: the first compression of a factor set or batch times every
+ * valid QR, pivoted-QR and tail_b choice of each launch step on that step's
+ * own data and keeps the fastest (cached per device and launch shape for
+ * the life of the process); that call therefore waits for its stream and
+ * must not be made while the stream is being captured.  Setting the
+ * environment variable HBS_AUTOTUNE=0 before creating the handle keeps the
+ * built-in heuristic instead. */
+#define HBS_PLAN_COLS 18
+hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows, int32_t* nrows);
 
 /* Storage of the factors (quantity (4) of section 5): the number of FP64
  * values of every U_tau, V_tau (m_tau x k), D_tau (m_tau x m_tau) and of

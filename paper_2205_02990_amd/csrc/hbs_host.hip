@@ -5,10 +5,13 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <vector>
 
 #include "hbs_internal.h"
@@ -66,6 +69,10 @@ struct Instance {
 
 struct Launch {
   hbs::SweepArgs args;
+  // tile choices (heuristic until the autotuner has run)
+  hbs::LqChoice lq{-1, 0};
+  int col = -1;
+  int tailb = -1;
 };
 
 struct Mark {
@@ -91,6 +98,8 @@ struct BatchImpl {
   hipStream_t last = nullptr;
   // graph of the whole sweep, captured on first use
   bool use_graph = true;
+  bool autotune = true;  // time the tile choices on the first sweep
+  bool tuned = false;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cstream = nullptr;  // capture stream
   // tracing
@@ -360,19 +369,136 @@ hbs_status build_sweep(BatchImpl* b) {
 hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
   for (const Launch& ln : b->launches) {
     HIP_TRY(b->mark_begin(ln.args.root ? 5 : 0, st));
-    HIP_TRY(hbs::launch_lq(ln.args, st));
+    HIP_TRY(hbs::launch_lq(ln.args, ln.lq, st));
     HIP_TRY(b->mark_end(st));
     if (ln.args.root) continue;
     HIP_TRY(b->mark_begin(1, st));
-    HIP_TRY(hbs::launch_col(ln.args, st));
+    HIP_TRY(hbs::launch_col(ln.args, ln.col, st));
     HIP_TRY(b->mark_end(st));
     for (int part = 0; part < 3; ++part) {
       HIP_TRY(b->mark_begin(2 + part, st));
-      HIP_TRY(hbs::launch_tail(ln.args, part, st));
+      HIP_TRY(hbs::launch_tail(ln.args, part, part == 1 ? ln.tailb : -1, st));
       HIP_TRY(b->mark_end(st));
     }
   }
   return HBS_OK;
+}
+
+// ---- autotuner ----------------------------------------------------------
+// The first sweep of a batch runs step by step; for the QR, the pivoted QR
+// and the tail_b products it times every valid tile choice on the step's own
+// data (twice each, the faster run counts) and keeps the fastest, then runs
+// the chosen one so that the step's outputs are its.  (tail_a and tail_c run
+// once: tail_c updates the parent panels in place.)  Choices are cached per
+// device and launch shape for the life of the process, so later batches of
+// the same shapes reuse them without timing.
+struct TuneKey {
+  int dev, kind, mmax, mmin, s, k, nboxes, mixed, root;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(dev, kind, mmax, mmin, s, k, nboxes, mixed, root) <
+           std::tie(o.dev, o.kind, o.mmax, o.mmin, o.s, o.k, o.nboxes, o.mixed, o.root);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;  // kind 0: (lq cfg, ns); 1: (col cfg, 0); 2: (tail_b variant, 0)
+
+TuneKey tune_key(int dev, int kind, const hbs::SweepArgs& a) {
+  return TuneKey{dev, kind, a.mmax, a.mmin, a.s, a.k, a.nboxes, a.mixed, a.root};
+}
+
+bool tune_lookup(const TuneKey& key, std::pair<int, int>* v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(key);
+  if (it == g_tune.end()) return false;
+  *v = it->second;
+  return true;
+}
+
+void tune_store(const TuneKey& key, std::pair<int, int> v) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = v;
+}
+
+// Device time of fn() on the stream: the faster of two runs.
+template <class F>
+hipError_t time_twice(F fn, hipEvent_t e0, hipEvent_t e1, hipStream_t st, float* ms) {
+  float best = 1e30f;
+  for (int r = 0; r < 2; ++r) {
+    hipError_t e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = fn();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return e;
+    best = std::min(best, t);
+  }
+  *ms = best;
+  return hipSuccess;
+}
+
+hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (Launch& ln : b->launches) {
+    if (e != hipSuccess) break;
+    const hbs::SweepArgs& a = ln.args;
+    std::pair<int, int> v;
+    // QR of the test blocks
+    if (tune_lookup(tune_key(dev, 0, a), &v)) {
+      ln.lq = hbs::LqChoice{v.first, v.second};
+    } else {
+      hbs::LqChoice cand[64];
+      const int n = hbs::lq_candidates(a, cand, 64);
+      float best = 1e30f;
+      for (int i = 0; i < n && e == hipSuccess; ++i) {
+        float t = 0.0f;
+        e = time_twice([&] { return hbs::launch_lq(a, cand[i], st); }, e0, e1, st, &t);
+        if (e == hipSuccess && t < best) best = t, ln.lq = cand[i];
+      }
+      if (e == hipSuccess && ln.lq.cfg >= 0) tune_store(tune_key(dev, 0, a), {ln.lq.cfg, ln.lq.ns});
+    }
+    if (e == hipSuccess) e = hbs::launch_lq(a, ln.lq, st);
+    if (e != hipSuccess || a.root) continue;
+    // truncated pivoted QR
+    if (tune_lookup(tune_key(dev, 1, a), &v)) {
+      ln.col = v.first;
+    } else {
+      int cand[16];
+      const int n = hbs::col_candidates(a, cand, 16);
+      float best = 1e30f;
+      for (int i = 0; i < n && e == hipSuccess; ++i) {
+        float t = 0.0f;
+        e = time_twice([&] { return hbs::launch_col(a, cand[i], st); }, e0, e1, st, &t);
+        if (e == hipSuccess && t < best) best = t, ln.col = cand[i];
+      }
+      if (e == hipSuccess && ln.col >= 0) tune_store(tune_key(dev, 1, a), {ln.col, 0});
+    }
+    if (e == hipSuccess) e = hbs::launch_col(a, ln.col, st);
+    if (e == hipSuccess) e = hbs::launch_tail(a, 0, -1, st);
+    // the k-wide terms
+    if (e == hipSuccess && tune_lookup(tune_key(dev, 2, a), &v)) {
+      ln.tailb = v.first;
+    } else if (e == hipSuccess) {
+      float best = 1e30f;
+      for (int var = 0; var < 2 && e == hipSuccess; ++var) {
+        float t = 0.0f;
+        e = time_twice([&] { return hbs::launch_tail(a, 1, var, st); }, e0, e1, st, &t);
+        if (e == hipSuccess && t < best) best = t, ln.tailb = var;
+      }
+      if (e == hipSuccess) tune_store(tune_key(dev, 2, a), {ln.tailb, 0});
+    }
+    if (e == hipSuccess) e = hbs::launch_tail(a, 1, ln.tailb, st);
+    if (e == hipSuccess) e = hbs::launch_tail(a, 2, -1, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return e;
 }
 
 // Point the panel-source slots at the caller's inputs, then run the sweep:
@@ -380,6 +506,12 @@ hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
 hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
   HIP_TRY(hipMemcpyAsync(b->d_src, b->h_src, sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st));
   b->last = st;
+  if (b->autotune && !b->tuned) {
+    // the first sweep picks the tiles; the sweep below (graph capture or
+    // direct launches) then runs with them
+    HIP_TRY(tune_sweep(b, st));
+    b->tuned = true;
+  }
   if (b->prof || !b->use_graph) return enqueue_sweep(b, st);
   if (!b->gexec) {
     // captured once on a private stream (the default stream cannot be
@@ -417,6 +549,10 @@ hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t
   std::shared_ptr<BatchImpl> b(new (std::nothrow) BatchImpl);
   if (!b) return HBS_ENOMEM;
   b->prec = prec;
+  {
+    const char* ev = std::getenv("HBS_AUTOTUNE");  // "0": keep the built-in tile heuristic
+    b->autotune = !(ev && ev[0] == '0');
+  }
   HIP_TRY(b->alloc((void**)&b->flag, sizeof(int32_t)));
   HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));
   b->inst.resize(count);
@@ -745,6 +881,31 @@ hbs_status hbs_root(const hbs_factors* f, const double** D0, int32_t* rows) {
   const Instance& in = inst_of(f);
   *D0 = in.D0;
   *rows = in.n0;
+  return HBS_OK;
+}
+
+hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows, int32_t* nrows) {
+  if (!f || !nrows || max_rows < 0 || (max_rows > 0 && !rows)) return HBS_EINVAL;
+  const BatchImpl* b = f->b.get();
+  *nrows = (int32_t)b->launches.size();
+  for (int32_t i = 0; i < *nrows && i < max_rows; ++i) {
+    const Launch& ln = b->launches[i];
+    const hbs::SweepArgs& a = ln.args;
+    int32_t* r = rows + (size_t)i * HBS_PLAN_COLS;
+    for (int c = 0; c < HBS_PLAN_COLS; ++c) r[c] = 0;
+    r[0] = i, r[1] = a.nboxes, r[2] = a.mmax, r[3] = a.s, r[4] = a.k, r[5] = a.root, r[6] = b->tuned ? 1 : 0;
+    const hbs::LqChoice lq = ln.lq.cfg >= 0 ? ln.lq : hbs::lq_default(a);
+    int v[6] = {0, 0, 0, 0, 0, 0};
+    if (lq.cfg >= 0) hbs::lq_describe(lq, v);
+    for (int c = 0; c < 6; ++c) r[7 + c] = v[c];
+    if (!a.root) {
+      const int col = ln.col >= 0 ? ln.col : hbs::col_default(a);
+      int w[4] = {0, 0, 0, 0};
+      if (col >= 0) hbs::col_describe(col, w);
+      for (int c = 0; c < 4; ++c) r[13 + c] = w[c];
+      r[17] = ln.tailb >= 0 ? ln.tailb : (a.nboxes < 256 ? 1 : 0);
+    }
+  }
   return HBS_OK;
 }
 

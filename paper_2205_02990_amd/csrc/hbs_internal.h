@@ -65,16 +65,33 @@ struct ApplyArgs {
 
 bool side_supported(int mmin, int mmax, int s, int k, bool root);
 hipError_t prepare_side_kernels();
+// Launch choices the autotuner picks among: a QR tile class (index into the
+// compiled classes) with a number of sample-row chunks per box; cfg < 0 means
+// the built-in heuristic.
+struct LqChoice {
+  int cfg, ns;
+};
+// The valid choices for a launch (up to max), the heuristic's, and the tile
+// shape of a choice (lq: nt, cpr, ra, rs, cpl, ns; col: nt, cpr, rpl, cpl).
+int lq_candidates(const SweepArgs& a, LqChoice* out, int max);
+int col_candidates(const SweepArgs& a, int* out, int max);
+LqChoice lq_default(const SweepArgs& a);
+int col_default(const SweepArgs& a);
+void lq_describe(LqChoice c, int* v);
+void col_describe(int c, int* v);
 // QR of the test blocks, reflectors applied to the samples, Y Omega^dagger
 // (both sides of every box; the root's one side)
-hipError_t launch_lq(const SweepArgs& a, hipStream_t st);
+hipError_t launch_lq(const SweepArgs& a, LqChoice ch, hipStream_t st);
 // N of a factor set's tree (host)
 int64_t factors_n(const hbs_factors* f);
 // truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
-hipError_t launch_col(const SweepArgs& a, hipStream_t st);
-// the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c)
+// (cfg: index of a column tile class, < 0 for the heuristic)
+hipError_t launch_col(const SweepArgs& a, int cfg, hipStream_t st);
+// the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c);
+// variant (tail_b only): 0 one workgroup per chain, 1 row blocks in
+// parallel with deeper K chunks, < 0 the heuristic (1 on levels of few boxes)
 size_t tail_workspace(int dld, int k);
-hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st);
+hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_dense_small(const double* A, int64_t lda, int32_t transA, const double* Bm, int64_t ldb,

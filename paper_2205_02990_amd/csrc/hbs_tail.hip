@@ -178,7 +178,7 @@ size_t tail_workspace(int dld, int k) {
   return 6 * (size_t)dld * k + 2 * (size_t)((dld + 63) / 64) * k * k;
 }
 
-hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
+hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
   if (part == 0) {
@@ -189,7 +189,8 @@ hipError_t launch_tail(const SweepArgs& a, int part, hipStream_t st) {
       hipLaunchKernelGGL(tail_a_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
   } else if (part == 1) {
     // few boxes: latency bound, row blocks in parallel and deeper K chunks
-    if (a.nboxes < 256)
+    if (variant < 0) variant = a.nboxes < 256 ? 1 : 0;
+    if (variant == 1)
       hipLaunchKernelGGL(tail_b_kernel<32>, dim3(a.nboxes, 2 * mt), dim3(kGemmThreads), 0, st, a);
     else
       hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);

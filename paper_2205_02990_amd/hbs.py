@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhbs.so")
 
 HBS_OK, HBS_EINVAL, HBS_ENOMEM, HBS_EDEVICE, HBS_ENUMERIC, HBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "split": 1, "fp32_split": 1, "bf16": 2}
+PLAN_COLS = 18  # HBS_PLAN_COLS
 
 _lib = None
 _hip = None
@@ -74,6 +75,7 @@ def load():
                                        ctypes.POINTER(P), ctypes.POINTER(I64), I32, VP, ctypes.POINTER(P)]),
         "hbs_floats_per_dof": (I32, [P, ctypes.POINTER(ctypes.c_double)]),
         "hbs_power_norm": (I32, [P, VP, VP, I64, VP, I32, ctypes.POINTER(ctypes.c_double), VP]),
+        "hbs_sweep_plan": (I32, [P, ctypes.POINTER(I32), I32, ctypes.POINTER(I32)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
@@ -220,6 +222,24 @@ class Factors:
 
     def _matvec(self):
         return ctypes.cast(load().hbs_matvec_factors, ctypes.c_void_p), self._h
+
+    def plan(self) -> list:
+        """Tile plan of the sweep, one dict per launch step (hbs_sweep_plan)."""
+        lib = load()
+        n = ctypes.c_int32()
+        _check(lib.hbs_sweep_plan(self._h, None, 0, ctypes.byref(n)), "hbs_sweep_plan")
+        rows = (ctypes.c_int32 * (PLAN_COLS * max(n.value, 1)))()
+        _check(lib.hbs_sweep_plan(self._h, rows, n.value, ctypes.byref(n)), "hbs_sweep_plan")
+        out = []
+        for i in range(n.value):
+            r = rows[PLAN_COLS * i:PLAN_COLS * (i + 1)]
+            out.append({"step": r[0], "boxes": r[1], "mmax": r[2], "s": r[3], "k": r[4], "root": bool(r[5]),
+                        "tuned": bool(r[6]), "lq": {"threads": r[7], "lanes_per_row": r[8], "test_slots": r[9],
+                                                    "sample_slots": r[10], "col_slots": r[11], "chunks": r[12]},
+                        "col": None if r[5] else {"threads": r[13], "lanes_per_row": r[14], "row_slots": r[15],
+                                                  "col_slots": r[16]},
+                        "tail_b": None if r[5] else r[17]})
+        return out
 
     def root(self, stream=None) -> torch.Tensor:
         p, n = ctypes.c_void_p(), ctypes.c_int32()

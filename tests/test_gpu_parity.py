@@ -280,3 +280,35 @@ def test_compress_into_reuses_factor_set_with_ld(hbs):
     f.check()
     G = case["G"]
     assert rel(host(f.apply(dev(G))), ohbs.apply(case["gen"], G)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,k,leaf,s", [(3001, 16, 32, 58), (4096, 32, 64, 106)])
+def test_autotuned_and_heuristic_tiles_agree(hbs, n, k, leaf, s, monkeypatch):
+    """The tile autotuner (first compression) and the built-in heuristic
+    (HBS_AUTOTUNE=0) both reproduce the oracle; the plan reports the choice."""
+    case = synthetic_case(n, k, leaf, s, extra=(91,))
+    orc = ohbs.compress(case["levels"], k, case["Om"], case["Y"], case["Ps"], case["Z"])
+    G = case["G"]
+    ref = ohbs.apply(orc, G)
+    args = [dev(case[x]) for x in ("Om", "Y", "Ps", "Z")]
+    tree = hbs.Tree(n, leaf)
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("HBS_AUTOTUNE", mode)
+        f = hbs.Factors.create(tree, k, s)
+        assert not any(p["tuned"] for p in f.plan())
+        f.compress_into(*args)
+        f.check()
+        plan = f.plan()
+        assert len(plan) == tree.levels + 1 and plan[-1]["root"]
+        assert all(p["tuned"] for p in plan) == (mode == "1")
+        for p in plan:
+            lq = p["lq"]
+            assert lq["threads"] // lq["lanes_per_row"] * lq["test_slots"] >= p["mmax"]
+            assert lq["lanes_per_row"] * lq["col_slots"] >= p["s"]
+        out[mode] = host(f.apply(dev(G)))
+        e = rel(out[mode], ref)
+        print(f"[parity] autotune={mode} n={n}: vs oracle {e:.2e}; plan "
+              f"{[(p['lq']['threads'], p['lq']['chunks'], p['tail_b']) for p in plan]}", flush=True)
+        assert e <= 1e-12
+    assert rel(out["1"], out["0"]) <= 1e-12
