@@ -361,6 +361,7 @@ def main():
     plan = f.plan()
     tiles = [f"step {p['step']}: {p['boxes']} boxes m<={p['mmax']} lq {p['lq']['threads']}t/{p['lq']['lanes_per_row']}l "
              f"{p['lq']['test_slots']}x{p['lq']['sample_slots']}x{p['lq']['col_slots']} chunks {p['lq']['chunks']}"
+             + (f" cap {p['lq']['waves_per_simd_cap']}w" if p['lq']['waves_per_simd_cap'] else "")
              + ("" if p["root"] else f", col {p['col']['threads']}t/{p['col']['lanes_per_row']}l "
                 f"{p['col']['row_slots']}x{p['col']['col_slots']}, tail_b {p['tail_b']}")
              for p in plan]

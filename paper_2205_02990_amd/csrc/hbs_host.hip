@@ -895,9 +895,10 @@ hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows,
     for (int c = 0; c < HBS_PLAN_COLS; ++c) r[c] = 0;
     r[0] = i, r[1] = a.nboxes, r[2] = a.mmax, r[3] = a.s, r[4] = a.k, r[5] = a.root, r[6] = b->tuned ? 1 : 0;
     const hbs::LqChoice lq = ln.lq.cfg >= 0 ? ln.lq : hbs::lq_default(a);
-    int v[6] = {0, 0, 0, 0, 0, 0};
+    int v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (lq.cfg >= 0) hbs::lq_describe(lq, v);
     for (int c = 0; c < 6; ++c) r[7 + c] = v[c];
+    r[18] = v[6];
     if (!a.root) {
       const int col = ln.col >= 0 ? ln.col : hbs::col_default(a);
       int w[4] = {0, 0, 0, 0};
