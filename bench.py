@@ -363,7 +363,9 @@ def main():
              f"{p['lq']['test_slots']}x{p['lq']['sample_slots']}x{p['lq']['col_slots']} chunks {p['lq']['chunks']}"
              + (f" cap {p['lq']['waves_per_simd_cap']}w" if p['lq']['waves_per_simd_cap'] else "")
              + ("" if p["root"] else f", col {p['col']['threads']}t/{p['col']['lanes_per_row']}l "
-                f"{p['col']['row_slots']}x{p['col']['col_slots']}, tail_b {p['tail_b']}")
+                f"{p['col']['row_slots']}x{p['col']['col_slots']}"
+                + (f" cap {p['col']['waves_per_simd_cap']}w" if p['col']['waves_per_simd_cap'] else "")
+                + f", tail_b {p['tail_b']}")
              for p in plan]
     log(("autotuned" if plan and plan[0]["tuned"] else "heuristic") + " tiles:\n  " + "\n  ".join(tiles))
 

@@ -204,7 +204,8 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
  * column slots, sample-row chunks per box), pivoted-QR tile (threads, lanes
  * per row, sketch-row slots, column slots), tail_b variant (0 one
  * workgroup per chain, 1 row blocks in parallel), QR register cap (the
- * fewest waves per SIMD its registers leave room for; 0 for none).
+ * fewest waves per SIMD its registers leave room for; 0 for none),
+ * pivoted-QR register cap.
  *
  * Autotuning: the first compression of a factor set or batch times every
  * valid QR, pivoted-QR and tail_b choice of each launch step on that step's
@@ -213,7 +214,7 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
  * must not be made while the stream is being captured.  Setting the
  * environment variable HBS_AUTOTUNE=0 before creating the handle keeps the
  * built-in heuristic instead. */
-#define HBS_PLAN_COLS 19
+#define HBS_PLAN_COLS 20
 hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows, int32_t* nrows);
 
 /* Storage of the factors (quantity (4) of section 5): the number of FP64

@@ -901,9 +901,10 @@ hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows,
     r[18] = v[6];
     if (!a.root) {
       const int col = ln.col >= 0 ? ln.col : hbs::col_default(a);
-      int w[4] = {0, 0, 0, 0};
+      int w[5] = {0, 0, 0, 0, 0};
       if (col >= 0) hbs::col_describe(col, w);
       for (int c = 0; c < 4; ++c) r[13 + c] = w[c];
+      r[19] = w[4];
       r[17] = ln.tailb >= 0 ? ln.tailb : (a.nboxes < 256 ? 1 : 0);
     }
   }

@@ -73,7 +73,7 @@ struct LqChoice {
 };
 // The valid choices for a launch (up to max), the heuristic's, and the tile
 // shape of a choice (lq: nt, cpr, ra, rs, cpl, ns, register cap in waves per
-// SIMD or 0; col: nt, cpr, rpl, cpl).
+// SIMD or 0; col: nt, cpr, rpl, cpl, register cap).
 int lq_candidates(const SweepArgs& a, LqChoice* out, int max);
 int col_candidates(const SweepArgs& a, int* out, int max);
 LqChoice lq_default(const SweepArgs& a);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libhbs.so")
 
 HBS_OK, HBS_EINVAL, HBS_ENOMEM, HBS_EDEVICE, HBS_ENUMERIC, HBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "split": 1, "fp32_split": 1, "bf16": 2}
-PLAN_COLS = 19  # HBS_PLAN_COLS
+PLAN_COLS = 20  # HBS_PLAN_COLS
 
 _lib = None
 _hip = None
@@ -238,7 +238,7 @@ class Factors:
                                                     "sample_slots": r[10], "col_slots": r[11], "chunks": r[12],
                                                     "waves_per_simd_cap": r[18]},
                         "col": None if r[5] else {"threads": r[13], "lanes_per_row": r[14], "row_slots": r[15],
-                                                  "col_slots": r[16]},
+                                                  "col_slots": r[16], "waves_per_simd_cap": r[19]},
                         "tail_b": None if r[5] else r[17]})
         return out
 
