@@ -203,10 +203,11 @@ __device__ __forceinline__ void slice_regs(const double (&x)[kSlicePer], int c, 
 }
 
 // Contracted lengths covered: the products here contract over the rows of one
-// box (K = m_tau <= 128), two chunks of kSliceK.
+// box (K = m_tau <= 128), at most two chunks of kSliceK; launches whose boxes
+// have at most 64 rows instantiate one chunk (half the staging registers).
 constexpr int kSliceChunks = 2;
 
-template <int S>
+template <int S, int KCH = kSliceChunks>
 __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, const double* __restrict__ L, int64_t ldl,
                           const double* __restrict__ R, int64_t ldr, double beta, const double* C0, int64_t ldc0,
                           double* C, int64_t ldc, SliceSmem<S>& sm) {
@@ -221,10 +222,10 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
       // scales (largest magnitude of each row of L^T and each column of R)
       // come from the same registers
       const bool oki = i0 + c < M, okj = j0 + c < N;
-      double xa[kSliceChunks][kSlicePer], xb[kSliceChunks][kSlicePer];
+      double xa[KCH][kSlicePer], xb[KCH][kSlicePer];
       double ma = 0.0, mb = 0.0;
 #pragma unroll
-      for (int h = 0; h < kSliceChunks; ++h)
+      for (int h = 0; h < KCH; ++h)
 #pragma unroll
         for (int u = 0; u < kSlicePer; ++u) {
           const int kk = kSliceK * h + kSlicePer * g + u;
@@ -257,7 +258,7 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
 #pragma unroll
         for (int d = 0; d < S; ++d) acc[b][d] = gemm_i4{0, 0, 0, 0};
 #pragma unroll
-      for (int h = 0; h < kSliceChunks; ++h) {
+      for (int h = 0; h < KCH; ++h) {
         if (kSliceK * h >= K) break;
         slice_regs<S>(xa[h], c, g, sm.ea[c], sm.u.q.As);
         slice_regs<S>(xb[h], c, g, sm.eb[c], sm.u.q.Bs);

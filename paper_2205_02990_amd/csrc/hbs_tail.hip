@@ -58,12 +58,12 @@ struct TailWs {
 };
 
 // C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
-template <bool MIXED>
+template <bool MIXED, int KCH>
 __device__ __forceinline__ void bulk(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
                             const double* R, int64_t ldr, double beta, const double* C0, int64_t ldc0, double* C,
                             int64_t ldc) {
   if constexpr (MIXED)
-    sliced_lt<kSlices>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
+    sliced_lt<kSlices, KCH>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
   else
     mfma_gemm<16>(M, N, K, alpha, L, 1, ldl, R, ldr, 1, beta, C0, ldc0, C, ldc, sm.g);
 }
@@ -81,7 +81,7 @@ template <bool MIXED>
 constexpr int tail_threads() { return MIXED ? kSliceThreads : kGemmThreads; }
 
 // grid (boxes, 3 mt + 4 st): mt = row tiles of the box, st = 64-column tiles of s
-template <bool MIXED>
+template <bool MIXED, int KCH = kSliceChunks>
 __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs a) {
   __shared__ TailSmem<MIXED> sm;
   const BoxDesc& bx = a.box[blockIdx.x];
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs
     const bool useV = (which == kOm) || (which == kZ);
     const double* L = useV ? bx.V : bx.U;
     const double* P = ps.p[which] + bx.row0 * ld + c0;
-    bulk<MIXED>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
+    bulk<MIXED, KCH>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
     return;
   }
   const int which = y / mt, r0 = (y % mt) * 64;
@@ -145,7 +145,7 @@ __global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
 }
 
 // grid (boxes, mt^2 + 2 st)
-template <bool MIXED>
+template <bool MIXED, int KCH = kSliceChunks>
 __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs a) {
   __shared__ TailSmem<MIXED> sm;
   const BoxDesc& bx = a.box[blockIdx.x];
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs
   const double* L = which ? ws.H : ws.E;
   const double* P = ps.p[2 * which] + bx.row0 * ld + c0;  // Omega or Psi
   double* out = bx.np[2 * which + 1] + c0;                 // Y' or Z'
-  bulk<MIXED>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
+  bulk<MIXED, KCH>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
 }
 
 }  // namespace
@@ -183,7 +183,9 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
   if (part == 0) {
     const dim3 grid(a.nboxes, 3 * mt + 4 * sct);
-    if (a.mixed)
+    if (a.mixed && a.mmax <= kSliceK)
+      hipLaunchKernelGGL((tail_a_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
+    else if (a.mixed)
       hipLaunchKernelGGL(tail_a_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
     else
       hipLaunchKernelGGL(tail_a_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
@@ -196,7 +198,9 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
       hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
   } else {
     const dim3 grid(a.nboxes, mt * mt + 2 * sct);
-    if (a.mixed)
+    if (a.mixed && a.mmax <= kSliceK)
+      hipLaunchKernelGGL((tail_c_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
+    else if (a.mixed)
       hipLaunchKernelGGL(tail_c_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
     else
       hipLaunchKernelGGL(tail_c_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
