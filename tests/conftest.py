@@ -16,3 +16,14 @@ def pytest_configure(config):
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture
+def progress(capsys):
+    """Print a progress line past pytest's output capture, so that a long GPU
+    test shows it is alive even when run without -s."""
+    def say(*args, **kw):
+        kw["flush"] = True
+        with capsys.disabled():
+            print(*args, **kw)
+    return say

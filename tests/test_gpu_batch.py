@@ -102,15 +102,17 @@ def test_batch_rejects_bad_arguments(hbs):
 
 
 @pytest.mark.timeout(900)
-def test_batch512_full_size(hbs):
+def test_batch512_full_size(hbs, progress):
     """The 512-instance workload (N log-uniform in [2048, 32768], k in {16, 32},
     leaf 2k, s = 3k + 10) in one batch: every instance reproduces its
     generator; four sampled instances are compared with the oracle's own sweep."""
     wl = inputs.WORKLOADS["hbs_exact_batch512"]
     spec = inputs.batch_instances(wl["id"], wl["count"], wl["n_lo"], wl["n_hi"], wl["ks"])
-    print(f"[batch512] {len(spec)} instances, total N = {sum(x['n'] for x in spec)}", flush=True)
+    progress(f"[batch512] {len(spec)} instances, total N = {sum(x['n'] for x in spec)}")
     trees, gens, G, Om, Ps, Y, Z = [], [], [], [], [], [], []
-    for x in spec:
+    for j, x in enumerate(spec):
+        if j % 128 == 0:
+            progress(f"[batch512] drawing and sampling instance {j}")
         levels = otree.cluster_tree(x["n"], x["leaf_max"])
         rs = inputs.streams(wl["id"], extra=(x["index"],))
         gen = ohbs.from_generators(levels, inputs.synthetic_generators(rs[inputs.STREAM_GENERATOR],
@@ -124,14 +126,15 @@ def test_batch512_full_size(hbs):
         Y.append(dev(ohbs.apply(gen, om)))
         Z.append(dev(ohbs.apply(gen, ps, transpose=True)))
         trees.append(hbs.Tree(x["n"], x["leaf_max"]))
-    print("[batch512] inputs ready; compressing", flush=True)
+    progress("[batch512] inputs ready; compressing")
     ks, ss = [x["k"] for x in spec], [x["s"] for x in spec]
     worst = {}
     batches = {}
     for precision in ("fp64", "split"):
         b = hbs.Batch(trees, ks, ss, precision)
-        b.compress(Om, Y, Ps, Z)
+        b.compress(Om, Y, Ps, Z)  # the first sweep also autotunes the tiles
         b.factors(0).check()
+        progress(f"[batch512] {precision}: compressed; checking every instance")
         w = 0.0
         for i, x in enumerate(spec):
             AG = ohbs.apply(gens[i][1], G[i])
@@ -139,7 +142,7 @@ def test_batch512_full_size(hbs):
             w = max(w, e)
         worst[precision] = w
         batches[precision] = b
-        print(f"[batch512] {precision}: worst relative apply error vs generator {w:.3e}", flush=True)
+        progress(f"[batch512] {precision}: worst relative apply error vs generator {w:.3e}")
     # depth <= 10 here; the method's own rounding growth up the tree keeps
     # the oracle below 3e-11 at depth 11 with these parameters
     assert worst["fp64"] <= 1e-10
@@ -153,6 +156,6 @@ def test_batch512_full_size(hbs):
         orc = ohbs.compress(levels, x["k"], om, host(Y[i]), ps, host(Z[i]))
         OG = ohbs.apply(orc, G[i])
         e = {p: rel(host(batches[p].factors(i).apply(dev(G[i]))), OG) for p in batches}
-        print(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)}: vs oracle "
-              f"fp64 {e['fp64']:.3e}, split {e['split']:.3e}", flush=True)
+        progress(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)}: vs oracle "
+                 f"fp64 {e['fp64']:.3e}, split {e['split']:.3e}")
         assert e["fp64"] <= 1e-10 and e["split"] <= 1e-10

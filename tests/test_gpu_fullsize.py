@@ -55,10 +55,10 @@ def check_orthonormal(f, tree, k, tol=1e-12):
 
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("name", ["logkernel_ellipse_n65536_k50", "logkernel_ellipse_n262144_k64"])
-def test_logkernel_full_size(hbs, name):
+def test_logkernel_full_size(hbs, name, progress):
     wl = inputs.WORKLOADS[name]
     n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
-    print(f"[fullsize] {name}: N={n} k={k} leaf_max={leaf} s={s}", flush=True)
+    progress(f"[fullsize] {name}: N={n} k={k} leaf_max={leaf} s={s}")
     rs = inputs.streams(wl["id"])
     x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
     Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
@@ -78,7 +78,7 @@ def test_logkernel_full_size(hbs, name):
     TG = f.apply(dev(G)).cpu().numpy()
     AG_R = olog.sample(x, y, G, R)
     err = rel(TG[R], AG_R)
-    print(f"[fullsize] {name}: relative apply error on 256 rows x 8 probes {err:.3e}", flush=True)
+    progress(f"[fullsize] {name}: relative apply error on 256 rows x 8 probes {err:.3e}")
     assert err <= 1e-9
     TtG = f.apply(dev(G), transpose=True).cpu().numpy()
     assert rel(TtG[R], AG_R) <= 1e-9  # A is symmetric
@@ -88,7 +88,7 @@ def test_logkernel_full_size(hbs, name):
 
 
 @pytest.mark.timeout(600)
-def test_logkernel_n262144_precision_paths(hbs):
+def test_logkernel_n262144_precision_paths(hbs, progress):
     """The three precision paths on the N = 2^18 log-kernel workload, against
     dense oracle rows: FP64 samples with the split-precision sweep, and BF16
     samples with the FP64 sweep (bounds 1e-9 and 1e-4; the FP64 path itself
@@ -115,26 +115,26 @@ def test_logkernel_n262144_precision_paths(hbs):
     f = hbs.compress(tree, k, Omd, Yb, Psd, Zb)
     f.check()
     e_bf16 = rel(f.apply(dev(G)).cpu().numpy()[R], AG_R)
-    print(f"[fullsize] N={n}: split sweep {e_split:.3e}; bf16 sampler rows {e_samp:.3e}, "
-          f"bf16 samples + FP64 sweep {e_bf16:.3e}", flush=True)
+    progress(f"[fullsize] N={n}: split sweep {e_split:.3e}; bf16 sampler rows {e_samp:.3e}, "
+             f"bf16 samples + FP64 sweep {e_bf16:.3e}")
     assert e_split <= 1e-9
     assert e_samp <= 1e-4 and e_bf16 <= 1e-4
 
 
 @pytest.mark.timeout(900)
-def test_exact_rank_n4194304_full_size(hbs):
+def test_exact_rank_n4194304_full_size(hbs, progress):
     """Exact recovery of the 16-level exact-rank HBS matrix from samples that
     the oracle's Algorithm 1 draws from the known generator."""
     wl = inputs.WORKLOADS["hbs_exact_n4194304_k32"]
     n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
-    print(f"[fullsize] exact-rank N={n} k={k} leaf_max={leaf} s={s}: generating", flush=True)
+    progress(f"[fullsize] exact-rank N={n} k={k} leaf_max={leaf} s={s}: generating")
     levels = otree.cluster_tree(n, leaf)
     rs = inputs.streams(wl["id"])
     gen = inputs.synthetic_generators(rs[inputs.STREAM_GENERATOR], otree.leaf_sizes(levels), k)
     fac = ohbs.from_generators(levels, gen)
     tree = hbs.Tree(n, leaf)
     assert tree.levels == 16
-    print("[fullsize] sampling through the generator (oracle)", flush=True)
+    progress("[fullsize] sampling through the generator (oracle)")
     Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
     Omd = dev(Om)
     Yd = dev(ohbs.apply(fac, Om))
@@ -143,7 +143,7 @@ def test_exact_rank_n4194304_full_size(hbs):
     Psd = dev(Ps)
     Zd = dev(ohbs.apply(fac, Ps, transpose=True))
     del Ps
-    print("[fullsize] compressing", flush=True)
+    progress("[fullsize] compressing")
     f = hbs.Factors.create(tree, k, s)
     f.compress_into(Omd, Yd, Psd, Zd)
     f.check()
@@ -151,7 +151,7 @@ def test_exact_rank_n4194304_full_size(hbs):
     AG = ohbs.apply(fac, G)  # the oracle's Algorithm 1 on the generator
     TG = f.apply(dev(G)).cpu().numpy()
     err = rel(TG, AG)
-    print(f"[fullsize] exact-rank N={n}: relative apply error vs the generator {err:.3e}", flush=True)
+    progress(f"[fullsize] exact-rank N={n}: relative apply error vs the generator {err:.3e}")
     # The method itself passes rounding up the tree: the oracle's own error
     # on these inputs grows about 2.5x per level (1.5e-13 at depth 5, 6.7e-13
     # at 7, 3.9e-12 at 9, 2.5e-11 at 11), i.e. about 2e-9 at depth 16; the
@@ -166,7 +166,7 @@ def test_exact_rank_n4194304_full_size(hbs):
     fs.compress_into(Omd, Yd, Psd, Zd)
     fs.check()
     err_s = rel(fs.apply(dev(G)).cpu().numpy(), AG)
-    print(f"[fullsize] exact-rank N={n}: split path, relative apply error vs the generator {err_s:.3e}", flush=True)
+    progress(f"[fullsize] exact-rank N={n}: split path, relative apply error vs the generator {err_s:.3e}")
     # eight 7-bit slices give the split products FP64-level error, so the
     # split path meets the FP64 path's bound
     assert err_s <= 5e-9
@@ -183,7 +183,7 @@ def test_exact_rank_n4194304_full_size(hbs):
 
 
 @pytest.mark.timeout(600)
-def test_exact_rank_depth11_against_oracle(hbs):
+def test_exact_rank_depth11_against_oracle(hbs, progress):
     """The 16-level workload's parameters (k = 32, leaf 64, s = 106) at
     N = 131072 (11 levels), where the oracle runs the whole sweep: GPU and
     oracle each reproduce the generator to the method's accuracy at this
@@ -194,7 +194,7 @@ def test_exact_rank_depth11_against_oracle(hbs):
     gen = ohbs.from_generators(levels, inputs.synthetic_generators(rs[0], otree.leaf_sizes(levels), k))
     Om, Ps = inputs.gaussian(rs[1], n, s), inputs.gaussian(rs[2], n, s)
     Y, Z = ohbs.apply(gen, Om), ohbs.apply(gen, Ps, transpose=True)
-    print("[fullsize] depth-11 oracle sweep", flush=True)
+    progress("[fullsize] depth-11 oracle sweep")
     orc = ohbs.compress(levels, k, Om, Y, Ps, Z)
     tree = hbs.Tree(n, leaf)
     f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z))
@@ -203,7 +203,6 @@ def test_exact_rank_depth11_against_oracle(hbs):
     AG, OG = ohbs.apply(gen, G), ohbs.apply(orc, G)
     TG = f.apply(dev(G)).cpu().numpy()
     e_orc, e_gpu, e_par = rel(OG, AG), rel(TG, AG), rel(TG, OG)
-    print(f"[fullsize] depth 11: oracle {e_orc:.3e}, GPU {e_gpu:.3e} vs generator; GPU vs oracle {e_par:.3e}",
-          flush=True)
+    progress(f"[fullsize] depth 11: oracle {e_orc:.3e}, GPU {e_gpu:.3e} vs generator; GPU vs oracle {e_par:.3e}")
     assert e_orc <= 1e-10 and e_gpu <= 1e-10
     assert e_par <= 1e-10
