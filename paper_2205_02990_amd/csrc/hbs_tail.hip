@@ -57,6 +57,27 @@ struct TailWs {
   }
 };
 
+// XCD-aware tile order (tail_a, tail_c).  The workgroups of a
+// one-dimensional launch are dealt to the chip's 8 XCDs in turn (workgroup i
+// to XCD i % 8), and each XCD has its own L2.  The ny tiles of one box read
+// the same basis, W, X and panels, so they are given consecutive slots on one
+// XCD: box x + 8 (l / ny) and tile l % ny for workgroup i = 8 l + x.  The
+// grid holds ny tiles for every box of the box count rounded up to 8; the
+// padding workgroups return at once.  (tail_b's two chains share no operand
+// and keep the plain two-dimensional grid, which measured faster.)
+constexpr int kXcds = 8;
+
+struct XcdTile {
+  int box, y;
+};
+__device__ __forceinline__ XcdTile xcd_tile(int ny) {
+  const int i = blockIdx.x, x = i % kXcds, l = i / kXcds;
+  return XcdTile{x + kXcds * (l / ny), l % ny};
+}
+inline dim3 xcd_grid(int nboxes, int ny) {
+  return dim3((unsigned)(((nboxes + kXcds - 1) / kXcds) * kXcds * ny));
+}
+
 // C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
 template <bool MIXED, int KCH>
 __device__ __forceinline__ void bulk(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
@@ -84,10 +105,12 @@ constexpr int tail_threads() { return MIXED ? kSliceThreads : kGemmThreads; }
 template <bool MIXED, int KCH = kSliceChunks>
 __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs a) {
   __shared__ TailSmem<MIXED> sm;
-  const BoxDesc& bx = a.box[blockIdx.x];
-  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
   const int mt = (a.mmax + 63) / 64;
-  const int y = blockIdx.y;
+  const XcdTile tl = xcd_tile(3 * mt + 4 * ((a.s + 63) / 64));
+  if (tl.box >= a.nboxes) return;
+  const BoxDesc& bx = a.box[tl.box];
+  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
+  const int y = tl.y;
   if (y >= 3 * mt) {
     const int st = (s + 63) / 64;
     const int q = y - 3 * mt, which = q / st, c0 = (q % st) * 64;
@@ -148,10 +171,12 @@ __global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
 template <bool MIXED, int KCH = kSliceChunks>
 __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs a) {
   __shared__ TailSmem<MIXED> sm;
-  const BoxDesc& bx = a.box[blockIdx.x];
-  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
   const int mt = (a.mmax + 63) / 64;
-  const int y = blockIdx.y;
+  const XcdTile tl = xcd_tile(mt * mt + 2 * ((a.s + 63) / 64));
+  if (tl.box >= a.nboxes) return;
+  const BoxDesc& bx = a.box[tl.box];
+  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
+  const int y = tl.y;
   TailWs ws(bx.T, dld, k);
   if (y < mt * mt) {  // D = W - U T, one 64 x 64 tile
     const int r0 = (y / mt) * 64, c0 = (y % mt) * 64;
@@ -182,7 +207,7 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
   if (part == 0) {
-    const dim3 grid(a.nboxes, 3 * mt + 4 * sct);
+    const dim3 grid = xcd_grid(a.nboxes, 3 * mt + 4 * sct);
     if (a.mixed && a.mmax <= kSliceK)
       hipLaunchKernelGGL((tail_a_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
     else if (a.mixed)
@@ -197,7 +222,7 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
     else
       hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
   } else {
-    const dim3 grid(a.nboxes, mt * mt + 2 * sct);
+    const dim3 grid = xcd_grid(a.nboxes, mt * mt + 2 * sct);
     if (a.mixed && a.mmax <= kSliceK)
       hipLaunchKernelGGL((tail_c_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
     else if (a.mixed)
