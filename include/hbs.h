@@ -211,7 +211,9 @@ hbs_status hbs_profile_read(hbs_factors* f, double* ms, int64_t* launches, int32
  * valid QR, pivoted-QR and tail_b choice of each launch step on that step's
  * own data and keeps the fastest (cached per device and launch shape for
  * the life of the process); that call therefore waits for its stream and
- * must not be made while the stream is being captured.  Setting the
+ * must not be made while the stream is being captured.  A tile whose
+ * compiled code spills registers to scratch is never timed, chosen or
+ * launched, by the autotuner or the heuristic.  Setting the
  * environment variable HBS_AUTOTUNE=0 before creating the handle keeps the
  * built-in heuristic instead. */
 #define HBS_PLAN_COLS 20
