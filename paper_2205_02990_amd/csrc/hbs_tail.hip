@@ -57,25 +57,33 @@ struct TailWs {
   }
 };
 
-// XCD-aware tile order (tail_a, tail_c).  The workgroups of a
-// one-dimensional launch are dealt to the chip's 8 XCDs in turn (workgroup i
-// to XCD i % 8), and each XCD has its own L2.  The ny tiles of one box read
-// the same basis, W, X and panels, so they are given consecutive slots on one
-// XCD: box x + 8 (l / ny) and tile l % ny for workgroup i = 8 l + x.  The
-// grid holds ny tiles for every box of the box count rounded up to 8; the
-// padding workgroups return at once.  (tail_b's two chains share no operand
-// and keep the plain two-dimensional grid, which measured faster.)
+// XCD-aware tile order (tail_a, tail_c).  The workgroups of a launch are
+// dealt to the chip's 8 XCDs in turn, in dispatch order (workgroup i to XCD
+// i % 8), and each XCD has its own L2.  The ny tiles of one box read the same
+// basis, W, X and panels, so they are given consecutive slots on one XCD:
+// box x + 8 (l / ny) and tile l % ny for workgroup i = 8 l + x.  The grid
+// holds ny tiles for every box of the box count rounded up to 8; the padding
+// workgroups return at once.  The x extent is capped at 2^21 workgroups (a
+// multiple of 8, so i % 8 is still the XCD) and rows of y carry the rest,
+// which keeps grid x times workgroup size within the 32-bit launch limit at
+// any box count.  (tail_b's two chains share no operand and keep the plain
+// two-dimensional grid, which measured faster.)
 constexpr int kXcds = 8;
+constexpr int64_t kXcdGridX = (int64_t)1 << 21;
 
 struct XcdTile {
   int box, y;
 };
 __device__ __forceinline__ XcdTile xcd_tile(int ny) {
-  const int i = blockIdx.x, x = i % kXcds, l = i / kXcds;
-  return XcdTile{x + kXcds * (l / ny), l % ny};
+  // 32-bit index arithmetic: launch_tail refuses grids of 2^31 workgroups
+  const unsigned i = blockIdx.x + gridDim.x * blockIdx.y, l = i / kXcds;
+  return XcdTile{(int)(i % kXcds + kXcds * (l / (unsigned)ny)), (int)(l % (unsigned)ny)};
 }
+inline int64_t xcd_total(int nboxes, int ny) { return (int64_t)((nboxes + kXcds - 1) / kXcds) * kXcds * ny; }
 inline dim3 xcd_grid(int nboxes, int ny) {
-  return dim3((unsigned)(((nboxes + kXcds - 1) / kXcds) * kXcds * ny));
+  const int64_t total = xcd_total(nboxes, ny);
+  const int64_t gx = total < kXcdGridX ? total : kXcdGridX;
+  return dim3((unsigned)gx, (unsigned)((total + gx - 1) / gx));
 }
 
 // C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
@@ -206,6 +214,7 @@ size_t tail_workspace(int dld, int k) {
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
+  if (xcd_total(a.nboxes, 3 * mt + 4 * sct) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
   if (part == 0) {
     const dim3 grid = xcd_grid(a.nboxes, 3 * mt + 4 * sct);
     if (a.mixed && a.mmax <= kSliceK)
