@@ -291,7 +291,13 @@ def main():
     ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain copy kernel over MIB MiB (reference for HBM byte counters)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU run: turn the run_counter_collection.csv files of two rocprofv3 --pmc passes "
+                         "(FETCH_SIZE, WRITE_SIZE) of bench.py --copy-probe MIB into the lq_kernel traffic file")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 512, args.workload)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(multi-GPU sharding of the tree is a design note, not built)", file=sys.stderr)
@@ -410,6 +416,59 @@ def main():
         out["cpu_baseline"] = P.cpu()
         log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} rows/s on {out['cpu_baseline']['cores']} threads")
     print(json.dumps(out), flush=True)
+
+
+def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None):
+    """HBM bytes per lq_kernel launch from two rocprofv3 --pmc passes of
+    `bench.py --copy-probe MIB` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch).  Each counter is scaled by what it reads for the plain MIB MiB
+    copy of the same run; the per-level bytes average the last six sweeps
+    (after the autotuner's timing launches), each sweep's root launch left
+    out, matching the launches the roofline's time covers.  Written, with the
+    digest of the QR kernel's source, to the profiles file bench.py reads."""
+    import csv
+
+    from paper_2205_02990_amd import hbs
+
+    wl = inputs_workloads()[workload]
+    if wl["kind"] == "batch":
+        raise SystemExit("per-level traffic is summarised for single-instance workloads")
+    per = hbs.Tree(wl["n"], wl["leaf_max"]).levels + 1  # lq launches per sweep: the levels, then the root
+    res = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        with open(path) as fh:
+            rows = [r for r in csv.DictReader(fh) if r["Counter_Name"] == name]
+        copy = [float(r["Counter_Value"]) for r in rows if "MulFunctor" in r["Kernel_Name"]]
+        if not copy:
+            raise SystemExit(f"{path}: no copy-probe dispatch (run bench.py with --copy-probe)")
+        scale = mib * 1024.0 / (sum(copy) / len(copy))
+        lq = [r for r in rows if "lq_kernel" in r["Kernel_Name"]][-6 * per:]
+        sweeps = [lq[i:i + per] for i in range(0, len(lq) - len(lq) % per, per)]
+        vals = [[float(r["Counter_Value"]) * scale * 1024 for r in sw[:-1]] for sw in sweeps]
+        res[name] = dict(scale=scale, copy_kib=copy[0],
+                         per_level=[sum(v[i] for v in vals) / len(vals) for i in range(per - 1)])
+    fetch, write = res["FETCH_SIZE"]["per_level"], res["WRITE_SIZE"]["per_level"]
+    out = {"kernel": "lq_kernel", "workload": workload,
+           "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch),
+           "fetch_bytes_per_level": fetch, "write_bytes_per_level": write,
+           "fetch_scale": res["FETCH_SIZE"]["scale"], "write_scale": res["WRITE_SIZE"]["scale"],
+           "calibration": f"elementwise copy of {mib} MiB: FETCH_SIZE reads {res['FETCH_SIZE']['copy_kib']:.0f} KiB, "
+                          f"WRITE_SIZE {res['WRITE_SIZE']['copy_kib']:.0f} KiB per dispatch",
+           "source_digest": _side_digest(),
+           "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -f csv -d <dir> -o run -- python3 -u bench.py "
+                      f"--steps 3 --warmup 1 --no-cpu-baseline --copy-probe {mib}" +
+                      ("" if workload == "logkernel_ellipse_n65536_k50" else f" --workload {workload}")}
+    if dst is None:
+        dst = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"lq_kernel_{workload}_traffic.json")
+    with open(dst, "w") as fh:
+        json.dump(out, fh, indent=1)
+    log(f"wrote {dst}: {out['bytes_per_launch'] / 1e6:.1f} MB per lq launch")
+    return out
+
+
+def inputs_workloads():
+    import inputs
+    return inputs.WORKLOADS
 
 
 def _side_digest():

@@ -1,0 +1,72 @@
+"""Host logic of bench.py's counter summary (--traffic-from): the copy-probe
+calibration, the per-level averaging over the last six sweeps and the
+exclusion of each sweep's root launch, on synthetic counter files."""
+import csv
+import json
+import os
+
+import pytest
+
+import bench
+
+
+@pytest.fixture(autouse=True)
+def _library():
+    # the workload's level count comes from the library's own tree (host code)
+    from paper_2205_02990_amd import hbs
+    if not os.path.exists(hbs.LIB_PATH):
+        pytest.skip("libhbs.so not built (run python -m paper_2205_02990_amd.build)")
+
+FIELDS = ["Correlation_Id", "Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def write_counters(path, name, copy_kib, sweeps, per, value):
+    """One copy-probe dispatch, then `sweeps` sweeps of `per` lq launches
+    (levels, then the root) whose counter reads value(sweep, launch) KiB."""
+    rows = [dict(Kernel_Name="void at::native::vectorized_elementwise_kernel<4, at::native::MulFunctor<double>>",
+                 Counter_Name=name, Counter_Value=copy_kib)]
+    rows.append(dict(Kernel_Name="other_kernel", Counter_Name=name, Counter_Value=12345.0))
+    for sw in range(sweeps):
+        for j in range(per):
+            rows.append(dict(Kernel_Name=f"void hbs::lq_kernel<256, 4, 1, 1, 16, 0>(hbs::SweepArgs)",
+                             Counter_Name=name, Counter_Value=value(sw, j)))
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        for i, r in enumerate(rows):
+            w.writerow(dict(Correlation_Id=i, Dispatch_Id=i, **r))
+
+
+@pytest.mark.parametrize("mib", [512, 64])
+def test_traffic_summary(tmp_path, mib):
+    wl = "hbs_exact_n1024_k16"  # 5 levels below the root: 6 lq launches per sweep
+    per = 6
+    # FETCH reads half the copy's bytes (scale 2), WRITE all of them (scale 1)
+    f_csv, w_csv = tmp_path / "fetch.csv", tmp_path / "write.csv"
+    # 8 sweeps: the first two (tuning, warm-up) must not count
+    write_counters(f_csv, "FETCH_SIZE", mib * 1024 / 2, 8, per,
+                   lambda sw, j: 1e9 if sw < 2 else 100.0 * (j + 1) + (999.0 if j == per - 1 else 0.0))
+    write_counters(w_csv, "WRITE_SIZE", mib * 1024, 8, per,
+                   lambda sw, j: 1e9 if sw < 2 else 10.0 * (j + 1) + sw)
+    dst = tmp_path / "traffic.json"
+    out = bench.traffic_from_counters(str(f_csv), str(w_csv), mib, wl, dst=str(dst))
+    assert json.loads(dst.read_text()) == out
+    assert out["fetch_scale"] == pytest.approx(2.0) and out["write_scale"] == pytest.approx(1.0)
+    fetch = [2 * 100.0 * (j + 1) * 1024 for j in range(per - 1)]
+    mean_sw = sum(range(2, 8)) / 6
+    write = [(10.0 * (j + 1) + mean_sw) * 1024 for j in range(per - 1)]
+    assert out["fetch_bytes_per_level"] == pytest.approx(fetch)
+    assert out["write_bytes_per_level"] == pytest.approx(write)
+    assert out["bytes_per_launch"] == pytest.approx((sum(fetch) + sum(write)) / (per - 1))
+    assert out["source_digest"] == bench._side_digest()
+
+
+def test_traffic_summary_needs_the_copy_probe(tmp_path):
+    f_csv = tmp_path / "f.csv"
+    with open(f_csv, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        w.writerow(dict(Correlation_Id=0, Dispatch_Id=0, Kernel_Name="void hbs::lq_kernel<>", Counter_Name="FETCH_SIZE",
+                        Counter_Value=1.0))
+    with pytest.raises(SystemExit):
+        bench.traffic_from_counters(str(f_csv), str(f_csv), 512, "hbs_exact_n1024_k16", dst=str(tmp_path / "t.json"))
