@@ -6,8 +6,14 @@ Notation follows the paper.  Matrices are real, so A^* is the transpose.
 ``k`` is the width of every basis U_tau, V_tau (m_tau x k).  The sketch of a
 box uses the whole nullspace of its test matrix: P_tau = null(Omega_tau, r)
 with r = s - m_tau, which is the paper's own setting s = r + m (section 4.2,
-remark on conditioning); the rank-k basis is then U_tau = col(Y_tau P_tau, k),
-a truncated QR of the r-column sketch (section 2.4).
+remark on conditioning); the rank-k basis is then U_tau = col(Y_tau P_tau, k)
+of the r-column sketch (section 2.4), read in one of two ways:
+
+  truncation="qr"   the paper's truncated QR: Householder QR with column
+                    pivoting stopped after k steps (linalg.col);
+  truncation="svd"  the k leading left singular vectors of the sketch
+                    (linalg.col_svd), the truncation step of the oversampled
+                    range finder of section 2.3.
 
 Factor container (a plain dict):
   levels  cluster tree, ``levels[l]`` = list of (start, stop) ranges
@@ -38,7 +44,16 @@ def discrepancy(U, V, W, X):
     return (I - U @ U.T) @ W + U @ U.T @ ((I - V @ V.T) @ X).T
 
 
-def box_factors(Om, Y, Ps, Z, k):
+def truncate(B, k, truncation):
+    """col(B, k) under the chosen reading (module docstring)."""
+    if truncation == "qr":
+        return linalg.col(B, k)
+    if truncation == "svd":
+        return linalg.col_svd(B, k)
+    raise ValueError(f"unknown truncation {truncation!r}")
+
+
+def box_factors(Om, Y, Ps, Z, k, truncation="qr"):
     """The block of Algorithm 2 for one node tau on a level l > 0:
     P = null(Omega_tau, r), Q = null(Psi_tau, r) with r = s - m_tau
     (sections 2.4, 4.1), U = col(Y_tau P, k), V = col(Z_tau Q, k)
@@ -46,8 +61,8 @@ def box_factors(Om, Y, Ps, Z, k):
     m, s = Om.shape
     P = linalg.null(Om, s - m)
     Q = linalg.null(Ps, s - m)
-    U = linalg.col(Y @ P, k)
-    V = linalg.col(Z @ Q, k)
+    U = truncate(Y @ P, k, truncation)
+    V = truncate(Z @ Q, k, truncation)
     W = Y @ linalg.pinv(Om)
     X = Z @ linalg.pinv(Ps)
     D = discrepancy(U, V, W, X)
@@ -63,14 +78,15 @@ def reduced_samples(U, V, D, Om, Y, Ps, Z):
     return V.T @ Om, U.T @ (Y - D @ Om), U.T @ Ps, V.T @ (Z - D.T @ Ps)
 
 
-def compress(levels, k, Omega, Y, Psi, Z, keep_samples=False):
+def compress(levels, k, Omega, Y, Psi, Z, keep_samples=False, truncation="qr"):
     """Algorithm 2: compress level by level from the leaves (level L) to the
     root, given the test matrices Omega, Psi (N x s) and the samples
     Y = A Omega, Z = A^* Psi.
 
     Returns the factor dict (module docstring).  With ``keep_samples`` the dict
     also holds ``samples[l]`` = list of (Omega_tau, Y_tau, Psi_tau, Z_tau) used
-    on level l.
+    on level l.  ``truncation`` selects the reading of col ("qr" or "svd",
+    module docstring).
     """
     L = depth(levels)
     fac = {"levels": levels, "k": int(k), "U": {}, "V": {}, "D": {}, "D0": None}
@@ -83,7 +99,7 @@ def compress(levels, k, Omega, Y, Psi, Z, keep_samples=False):
             fac["samples"][lev] = cur
         Us, Vs, Ds, red = [], [], [], []
         for Om_t, Y_t, Ps_t, Z_t in cur:
-            U, V, D = box_factors(Om_t, Y_t, Ps_t, Z_t, k)
+            U, V, D = box_factors(Om_t, Y_t, Ps_t, Z_t, k, truncation)
             Us.append(U)
             Vs.append(V)
             Ds.append(D)

@@ -1,10 +1,12 @@
 """Dense primitives of sections 2.2-2.4 and the least-squares step of
 section 4.2 (oracle; test infrastructure only).
 
-Every routine is the textbook definition on top of LAPACK's unpivoted
-Householder QR (``scipy.linalg.qr``).  The remark closing section 2.4 explains
-why no pivoting is needed: these routines only see random matrices or products
-with random matrices.
+Every routine is the textbook definition on top of LAPACK: Householder QR
+(``scipy.linalg.qr``) and, for the second reading of col, the singular value
+decomposition (``scipy.linalg.svd``, driver dgesvd).  The remark closing
+section 2.4 explains why no pivoting is needed for null and the
+pseudo-inverse: these routines only see random matrices or products with
+random matrices.
 """
 from __future__ import annotations
 
@@ -24,6 +26,24 @@ def col(B: np.ndarray, k: int) -> np.ndarray:
     """
     Q, _, _ = sla.qr(B, mode="economic", pivoting=True)
     return Q[:, :k]
+
+
+def col_svd(B: np.ndarray, k: int) -> np.ndarray:
+    """col(B, k), section 2.4, read as truncation of the singular value
+    decomposition: the k leading left singular vectors of B, in order of
+    decreasing singular value.
+
+    Section 2.3 asks for orthonormal columns Q that make ||B - Q Q^* B||
+    small; among all k orthonormal columns the leading left singular vectors
+    make it smallest (Eckart-Young), and they depend only on B B^*, not on the
+    order or the particular mixture of B's columns.  For B = Y_tau P_tau with
+    the whole nullspace P_tau this is the oversampled range finder of section
+    2.3 (sample, then truncate), so the basis no longer depends on which k of
+    the sketch columns a pivoted QR happens to pick.  Signs of the singular
+    vectors are LAPACK's (any sign is equally valid).
+    """
+    U, _, _ = sla.svd(B, full_matrices=False, lapack_driver="gesvd")
+    return U[:, :k]
 
 
 def null(B: np.ndarray, k: int) -> np.ndarray:

@@ -154,6 +154,80 @@ def test_col_is_rank_revealing():
     assert abs(abs(U[:, 0] @ x) - 1.0) <= 1e-12
 
 
+def _known_svd(rng, m, n, sv):
+    """B = U0 diag(sv) W0^* with orthonormal U0 (m x len(sv)), W0 (n x len(sv))
+    drawn as inputs; the singular values are given, in any order."""
+    p = len(sv)
+    U0 = inputs.random_orthonormal(rng, m, p)
+    W0 = inputs.random_orthonormal(rng, n, p)
+    return U0, W0, (U0 * np.asarray(sv)) @ W0.T
+
+
+@pytest.mark.parametrize("m,n,k", [(64, 42, 32), (100, 60, 50), (32, 26, 16), (8, 12, 3)])
+def test_col_svd_closed_form(m, n, k):
+    """col by SVD truncation returns the k leading left singular vectors of a
+    matrix built from known singular triples (given out of order), up to sign,
+    and the Eckart-Young residuals: ||B - Q Q^* B||_F^2 = sum of the dropped
+    sigma_i^2 and ||B - Q Q^* B||_2 = sigma_{k+1}."""
+    rng = np.random.default_rng(m * 1000 + n + k)
+    p = min(m, n)
+    sv = np.geomspace(1.0, 1e-9, p) * (1.0 + 0.5 * rng.random(p))
+    sv = np.sort(sv)[::-1]
+    perm = rng.permutation(p)
+    U0, W0, B = _known_svd(rng, m, n, sv[perm])
+    Q = linalg.col_svd(B, k)
+    assert Q.shape == (m, k)
+    order = np.argsort(perm)  # order[i]: position of the i-th largest in the construction
+    for i in range(k):
+        u = U0[:, order[i]]
+        assert abs(abs(Q[:, i] @ u) - 1.0) <= 1e-9, i
+    assert np.linalg.norm(Q.T @ Q - np.eye(k)) <= 1e-14 * m
+    R = B - Q @ (Q.T @ B)
+    assert np.linalg.norm(R) == pytest.approx(np.sqrt(np.sum(sv[k:] ** 2)), rel=1e-6, abs=1e-15)
+    assert np.linalg.norm(R, 2) == pytest.approx(sv[k], rel=1e-6)
+
+
+def test_col_svd_depends_only_on_the_column_space_structure():
+    """Right-multiplying the sketch by any orthogonal matrix (reordering or
+    mixing its columns) leaves the SVD truncation unchanged, while the
+    pivoted-QR truncation moves with it when B is not of exact rank k."""
+    rng = np.random.default_rng(8)
+    m, n, k = 64, 42, 32
+    sv = np.geomspace(1.0, 1e-3, n)
+    _, _, B = _known_svd(rng, m, n, sv)
+    M = inputs.random_orthonormal(rng, n, n)
+    P1, P2 = linalg.col_svd(B, k), linalg.col_svd(B @ M, k)
+    assert np.linalg.norm(P1 @ P1.T - P2 @ P2.T, 2) <= 1e-12
+    Q1, Q2 = linalg.col(B, k), linalg.col(B @ M, k)
+    assert np.linalg.norm(Q1 @ Q1.T - Q2 @ Q2.T, 2) > 1e-6
+
+
+def test_col_svd_planted_mistakes_are_caught():
+    """Plausible slips in the SVD truncation fail the closed-form pin: the
+    trailing instead of the leading singular vectors, the right instead of
+    the left ones (a transposed operand), and the first k columns of B
+    orthonormalised (truncated QR without pivoting)."""
+    rng = np.random.default_rng(21)
+    m, k = 16, 5
+    sv = np.linspace(3.0, 0.1, m)
+    perm = rng.permutation(m)
+    U0, W0, B = _known_svd(rng, m, m, sv[perm])
+    order = np.argsort(perm)
+    want = U0[:, order[:k]]
+
+    def ok(Q):
+        return Q.shape == (m, k) and np.linalg.norm(Q @ Q.T - want @ want.T, 2) <= 1e-9
+
+    slips = {
+        "trailing vectors": lambda Bm, kk: np.linalg.svd(Bm)[0][:, -kk:],
+        "right vectors": lambda Bm, kk: np.linalg.svd(Bm)[2].T[:, :kk],
+        "first k columns": lambda Bm, kk: np.linalg.qr(Bm)[0][:, :kk],
+    }
+    assert ok(linalg.col_svd(B, k))
+    for name, fn in slips.items():
+        assert not ok(fn(B, k)), name
+
+
 # --------------------------------------------------------------------------
 # section 3.3 and Algorithm 1: telescoping factorization and apply
 # --------------------------------------------------------------------------
@@ -192,6 +266,7 @@ def test_generator_is_hbs_of_rank_k():
 # Algorithm 2: compression
 # --------------------------------------------------------------------------
 
+@pytest.mark.parametrize("truncation", ["qr", "svd"])
 @pytest.mark.parametrize("n,k,leaf,s,tol", [
     (1024, 16, 32, 58, 1e-12),   # the five-level exact-rank workload, full size
     (1000, 12, 24, 46, 1e-12),   # N not a power of two: uneven leaves
@@ -199,14 +274,33 @@ def test_generator_is_hbs_of_rank_k():
     (96, 8, 48, 58, 1e-12),      # one level below the root
     (32, 8, 15, 34, 1e-12),      # leaves of exactly k rows
 ])
-def test_exact_recovery_brute_force(n, k, leaf, s, tol):
+def test_exact_recovery_brute_force(n, k, leaf, s, tol, truncation):
     levels, gen, Om, Ps, _ = synthetic_problem(n, k, leaf, s)
     A = hbs.dense(gen)
     Y, Z = A @ Om, A.T @ Ps
-    fac = hbs.compress(levels, k, Om, Y, Ps, Z)
+    fac = hbs.compress(levels, k, Om, Y, Ps, Z, truncation=truncation)
     assert rel(hbs.dense(fac), A) <= tol
-    # storage: k-wide bases at every node, full diagonal blocks
-    assert hbs.floats_per_dof(fac) == hbs.floats_per_dof(gen)
+
+
+@pytest.mark.parametrize("n,k,leaf,s", [(1024, 16, 32, 58), (1000, 12, 24, 46), (96, 8, 48, 58),
+                                        (32, 8, 15, 34), (40, 4, 64, 52)])
+def test_floats_per_dof_closed_form(n, k, leaf, s):
+    """Storage (quantity (4) of section 5) counted from the tree alone: every
+    box tau stores U_tau, V_tau (m_tau x k) and D_tau (m_tau x m_tau), with
+    m_tau the leaf size at level L and 2k above; plus the root block D^(0)
+    (2k x 2k, or N x N for a single box)."""
+    levels, gen, Om, Ps, _ = synthetic_problem(n, k, leaf, s)
+    A = hbs.dense(gen)
+    fac = hbs.compress(levels, k, Om, A @ Om, Ps, A.T @ Ps)
+    L = tree.depth(levels)
+    total = 0
+    for lev in range(1, L + 1):
+        for a, b in levels[lev]:
+            m = (b - a) if lev == L else 2 * k
+            total += 2 * m * k + m * m
+    n0 = n if L == 0 else 2 * k
+    total += n0 * n0
+    assert hbs.floats_per_dof(fac) == total / n
 
 
 def test_root_only_is_least_squares():
@@ -253,6 +347,26 @@ def test_nothing_lost_and_in_sample():
             assert np.linalg.norm(R - V @ (V.T @ R)) <= 1e-12 * np.linalg.norm(Z_t)
     assert rel(hbs.apply(fac, Om), Y) <= 1e-12
     assert rel(hbs.apply(fac, Ps, transpose=True), Z) <= 1e-12
+
+
+def test_svd_truncation_error_stays_flat_to_depth_9():
+    """With the SVD reading of col the exact-rank error at the largest
+    workload's shape (k = 32, leaf 64, s = 106) stays near machine precision
+    through nine levels (section 5.4: little growth with depth), whereas the
+    pivoted-QR reading grows by a factor of about 2.5 per level."""
+    errs = {}
+    for depth in (5, 7, 9):
+        n = 64 * 2 ** depth
+        levels, gen, Om, Ps, rs = synthetic_problem(n, 32, 64, 106, wid=5)
+        Y, Z = hbs.apply(gen, Om), hbs.apply(gen, Ps, transpose=True)
+        G = inputs.probes(rs[3], n)
+        ref = hbs.apply(gen, G)
+        for tr in ("qr", "svd"):
+            fac = hbs.compress(levels, 32, Om, Y, Ps, Z, truncation=tr)
+            errs[tr, depth] = metrics.probe_rel_error(ref, hbs.apply(fac, G))
+    assert max(errs["svd", d] for d in (5, 7, 9)) <= 4e-13, errs
+    assert errs["svd", 9] <= 10 * errs["svd", 5], errs
+    assert errs["qr", 9] >= 10 * errs["svd", 9], errs
 
 
 def test_error_does_not_grow_with_depth():
@@ -369,6 +483,19 @@ def test_logkernel_rows_and_sample():
     idx = np.array([0, 5, 299, 150])
     assert rel(logkernel.sample(x, y, G, idx, block=3), A[idx] @ G) <= 1e-15
     assert rel(logkernel.sample(x, y, G, block=64), A @ G) <= 1e-15
+
+
+def test_probe_rel_error_hand_computed():
+    """|| (A_test - A_ref) G ||_F / || A_ref G ||_F on a case worked by hand:
+    A_ref G = [[3, 0], [0, 4]] (Frobenius norm 5), A_test G differs by
+    [[0, 1], [0, 0]] (norm 1), so the error is 1/5; arrays and callables
+    give the same number, and equal inputs give 0."""
+    ref = np.array([[3.0, 0.0], [0.0, 4.0]])
+    test = np.array([[3.0, 1.0], [0.0, 4.0]])
+    assert metrics.probe_rel_error(ref, test) == 0.2
+    G = np.eye(2)
+    assert metrics.probe_rel_error(lambda g: ref @ g, lambda g: test @ g, G) == 0.2
+    assert metrics.probe_rel_error(ref, ref) == 0.0
 
 
 def test_power_norm_estimate():
