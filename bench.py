@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark: HBS compression rows/s on one MI355X.
+"""Benchmark: HBS compression rows/s on one MI355X, mixed against FP64 path.
 
 One step = one full compression sweep (Algorithm 2: every level from the
 leaves to the root, all boxes of a level at once) of an N x N matrix from its
 samples {Omega, Y = A Omega, Psi, Z = A^* Psi}, which are resident in HBM when
-the timed region starts (for the batched workload: one sweep over all
-instances).  The samples come from a stand-in black box, timed separately
-like the paper's compression time without the matvec: the log-kernel sampler
-(default workload), or Algorithm 1 on a seeded exact-rank generator.
+the timed region starts; for the batched workload (the default: 512
+independent exact-rank instances of uneven N) one sweep covers every
+instance.  The samples come from a stand-in black box, timed separately like
+the paper's compression time without the matvec: Algorithm 1 on seeded
+exact-rank generators, or the log-kernel sampler.
+
+Both arithmetic paths run on the same inputs in one invocation: the
+split-precision path (bulk products from exact 7-bit integer slices on the
+int8 matrix cores) gives `value`, the plain FP64 path its own figures in
+`paths.fp64`; errors against the generator (and, in the tests, the oracle)
+are reported per path.
 
 Output: one JSON line on stdout (rank 0).  Progress goes to stderr.
 """
@@ -58,29 +65,60 @@ def tail_flops(m, s, k):
     return 8 * m * m * k + 8 * m * k * k + 12 * k * m * s
 
 
+def nominal_side(m, s, k):
+    """The fixed flop model used for every fraction reported: the literal
+    Algorithm 2 with LAPACK operation counts, per side (Omega/Y or Psi/Z) of
+    one box of m rows: Householder QR of the s x m test block, forming the k
+    null columns P, Y P, thin QR of Y P with its Q, the pseudo-inverse through
+    the explicit Q1 and Y Omega^dagger, the projections, and the parent
+    blocks.  Returns the terms by name."""
+    return {"qr": 2 * m * m * (s - m / 3), "form_p": 4 * s * k * m - 2 * k * m * m, "yp": 2 * m * s * k,
+            "thin_qr": 4 * m * k * k - 4 * k ** 3 / 3,
+            "pinv": 2 * s * m * m - 2 * m ** 3 / 3 + 2 * m * m * s + m ** 3,
+            "proj": 4 * m * m * k, "parent": 2 * m * m * s + 4 * k * m * s}
+
+
+def nominal_lq(m, s, k):
+    """The part of the fixed model the QR kernel carries out, per side: the
+    QR of the test block, the null columns applied to the samples (P, Y P)
+    and Y Omega^dagger."""
+    t = nominal_side(m, s, k)
+    return t["qr"] + t["form_p"] + t["yp"] + t["pinv"]
+
+
+def nominal_box(m, s, k):
+    """The fixed model for one box: both sides, plus 4 m^2 k to combine D."""
+    return 2 * sum(nominal_side(m, s, k).values()) + 4 * m * m * k
+
+
 def sweep_model(leaf_sizes, k, s):
     """Per-step flop totals by kernel class, algorithmic HBM bytes of the QR
     kernel, and the launch count of each per-level kernel."""
     L = int(round(math.log2(len(leaf_sizes))))
     lq = col = tail = 0.0
     lq_bytes = 0
+    nom = nom_lq = 0.0
     for lev in range(L, 0, -1):
         ms = leaf_sizes if lev == L else [2 * k] * (2 ** lev)
         for m in ms:
             lq += 2 * lq_flops(m, s)
             col += 2 * col_flops(m, s, k)
             tail += tail_flops(m, s, k)
+            nom += nominal_box(m, s, k)
+            nom_lq += 2 * nominal_lq(m, s, k)
             # each side reads its two m x s panels, writes W (m x m) and the
             # transposed m x (s - m) nullspace sketch
             lq_bytes += 2 * 8 * (2 * m * s + m * m + m * (s - m))
     m0 = 2 * k if L > 0 else leaf_sizes[0]
     root = lq_flops(m0, s)
+    t0 = nominal_side(m0, s, k)
+    nom += t0["qr"] + t0["pinv"]  # the root: D^(0) = Y Omega^dagger
     return {"lq": lq, "col": col, "tail": tail, "root": root, "launches": L,
-            "lq_bytes": lq_bytes}
+            "lq_bytes": lq_bytes, "nominal": nom, "nominal_lq": nom_lq}
 
 
 # --------------------------------------------------------------------------
-# CPU baseline (oracle on a bounded sample)
+# CPU baseline (the oracle on a bounded sample of the workload)
 # --------------------------------------------------------------------------
 
 def _threads():
@@ -89,24 +127,47 @@ def _threads():
     return int(max([i.get("num_threads", 1) for i in info if i.get("user_api") == "blas"] or [1]))
 
 
-def cpu_baseline(k, leaf_max, levels, Om, Y, Ps, Z, sub_level, what):
-    """Time the FP64 oracle's Algorithm 2 on the rows of the first node of
-    level `sub_level` (all of that subtree's levels, on its own rows)."""
+def _timed_oracle(jobs, single_thread=False):
+    """Time the FP64 oracle's Algorithm 2 on each (levels, k, Om, Y, Ps, Z)
+    job; returns (rows, seconds, threads used)."""
+    import threadpoolctl
+
+    from oracle import hbs as ohbs
+    rows = sum(j[2].shape[0] for j in jobs)
+    with threadpoolctl.threadpool_limits(1 if single_thread else None):
+        threads = _threads()
+        t0 = time.perf_counter()
+        for levels, k, Om, Y, Ps, Z in jobs:
+            ohbs.compress(levels, k, Om, Y, Ps, Z)
+        dt = time.perf_counter() - t0
+    return rows, dt, threads
+
+
+def _oracle_synthetic(inputs, n, k, leaf, s, rs):
+    """An exact-rank instance drawn and sampled by the oracle alone (CPU)."""
     from oracle import hbs as ohbs
     from oracle import tree as otree
-    a, b = levels[sub_level][0]
-    sub = otree.cluster_tree(b - a, leaf_max)
-    t0 = time.perf_counter()
-    ohbs.compress(sub, k, Om[a:b], Y[a:b], Ps[a:b], Z[a:b])
-    dt = time.perf_counter() - t0
-    return {"value": (b - a) / dt, "unit": "rows/s", "cores": _threads(), "kind": "oracle",
-            "sample": (f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of level {sub_level} "
-                       f"of {what} ({otree.depth(sub)} levels, all its boxes), {dt:.1f} s; "
-                       f"host os.cpu_count()={os.cpu_count()}")}
+    levels = otree.cluster_tree(n, leaf)
+    gen = ohbs.from_generators(levels, inputs.synthetic_generators(rs[inputs.STREAM_GENERATOR],
+                                                                  otree.leaf_sizes(levels), k))
+    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
+    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
+    return levels, k, Om, ohbs.apply(gen, Om), Ps, ohbs.apply(gen, Ps, transpose=True)
+
+
+def cpu_result(jobs, single_jobs, sample):
+    rows, dt, thr = _timed_oracle(jobs)
+    out = {"value": rows / dt, "unit": "rows/s", "cores": thr, "kind": "oracle",
+           "sample": f"{sample}; {rows} rows in {dt:.1f} s; host os.cpu_count()={os.cpu_count()}"}
+    if single_jobs:
+        r1, d1, _ = _timed_oracle(single_jobs, single_thread=True)
+        out["single_thread"] = {"value": r1 / d1, "unit": "rows/s", "cores": 1,
+                                "sample": f"{r1} rows in {d1:.1f} s (BLAS held to one thread)"}
+    return out
 
 
 # --------------------------------------------------------------------------
-# workloads: each returns the problem on the device and how to measure it
+# workloads: inputs on the device once, then a factor set per path
 # --------------------------------------------------------------------------
 
 class Problem:
@@ -136,36 +197,36 @@ def setup_logkernel(wl, args, hbs, torch, inputs, dev):
     P = Problem()
     P.sampler_ms = e0.elapsed_time(e1)
     tree = hbs.Tree(n, leaf)
-    f = hbs.Factors.create(tree, k, s, args.path)
     P.rows = n
-    P.compress = lambda: f.compress_into(Omd, Yd, Psd, Zd)
-    P.handle = f
     P.leaf_sets = [(tree.leaf_sizes(), k, s)]
     P.config = {"N": n, "k": k, "leaf_max": leaf, "leaf": tree.leaf_sizes()[0], "s": s, "levels": tree.levels,
                 "sampler": args.sampler}
     G = torch.from_numpy(inputs.probes(rs[inputs.STREAM_PROBES], n, 8)).to(dev)
 
-    def error():
-        AG, _ = hbs.sample_logkernel(xd, yd, G, G)
-        TG = f.apply(G)
-        e = float(torch.linalg.norm(TG - AG) / torch.linalg.norm(AG))
-        ins = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
-        pw = hbs.power_rel_error(f, hbs.LogKernelBox(xd, yd), *_power_starts(inputs, wl["id"], n, torch, dev))
-        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the black box on 8 Gaussian probes",
-                "power_rel_err": pw, "power_reference": "||A~ - A|| / ||A||, 20 power steps each (section 5)",
-                "floats_per_dof": f.floats_per_dof()}
-    P.error = error
+    def build(path):
+        f = hbs.Factors.create(tree, k, s, path, args.truncation)
+
+        def error():
+            AG, _ = hbs.sample_logkernel(xd, yd, G, G)
+            e = float(torch.linalg.norm(f.apply(G) - AG) / torch.linalg.norm(AG))
+            ins = float(torch.linalg.norm(f.apply(Omd) - Yd) / torch.linalg.norm(Yd))
+            pw = hbs.power_rel_error(f, hbs.LogKernelBox(xd, yd), *_power_starts(inputs, wl["id"], n, torch, dev))
+            return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the black box on 8 Gaussian probes",
+                    "power_rel_err": pw, "floats_per_dof": f.floats_per_dof()}
+        return (lambda: f.compress_into(Omd, Yd, Psd, Zd)), f, error
+    P.build = build
 
     def cpu():
         from oracle import logkernel as olog
         from oracle import tree as otree
         levels = otree.cluster_tree(n, leaf)
         a, b = levels[args.cpu_subtree_level][0]
-        rows = np.arange(a, b)
-        YZ = olog.sample(x, y, np.hstack((Om, Ps)), rows)  # the oracle's samples of those rows
-        Ysub, Zsub = np.zeros_like(Om), np.zeros_like(Ps)
-        Ysub[a:b], Zsub[a:b] = YZ[:, :s], YZ[:, s:]
-        return cpu_baseline(k, leaf, levels, Om, Ysub, Ps, Zsub, args.cpu_subtree_level, args.workload)
+        sub = otree.cluster_tree(b - a, leaf)
+        YZ = olog.sample(x, y, np.hstack((Om, Ps)), np.arange(a, b))  # the oracle's samples of those rows
+        job = (sub, k, Om[a:b], YZ[:, :s], Ps[a:b], YZ[:, s:])
+        return cpu_result([job], [], f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of "
+                                     f"level {args.cpu_subtree_level} of {args.workload} (all its "
+                                     f"{otree.depth(sub)} levels)")
     P.cpu = cpu
     return P
 
@@ -204,30 +265,32 @@ def setup_synthetic(wl, args, hbs, torch, inputs, dev):
     e1.record()
     torch.cuda.synchronize()
     P.sampler_ms = e0.elapsed_time(e1)
-    f = hbs.Factors.create(tree, k, s, args.path)
     P.rows = n
-    P.compress = lambda: f.compress_into(Om, Y, Ps, Z)
-    P.handle = f
     P.leaf_sets = [(tree.leaf_sizes(), k, s)]
     P.config = {"N": n, "k": k, "leaf_max": leaf, "leaf": tree.leaf_sizes()[0], "s": s, "levels": tree.levels,
                 "sampler": "Algorithm 1 on the generator"}
 
-    def error():
-        AG = A.apply(G)
-        e = float(torch.linalg.norm(f.apply(G) - AG) / torch.linalg.norm(AG))
-        ins = float(torch.linalg.norm(f.apply(Om) - Y) / torch.linalg.norm(Y))
-        pw = hbs.power_rel_error(f, A, *_power_starts(inputs, wl["id"], n, torch, dev))
-        return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the exact generator on 8 Gaussian probes",
-                "power_rel_err": pw, "power_reference": "||A~ - A|| / ||A||, 20 power steps each (section 5)",
-                "floats_per_dof": f.floats_per_dof()}
-    P.error = error
+    def build(path):
+        f = hbs.Factors.create(tree, k, s, path, args.truncation)
+
+        def error():
+            AG = A.apply(G)
+            e = float(torch.linalg.norm(f.apply(G) - AG) / torch.linalg.norm(AG))
+            ins = float(torch.linalg.norm(f.apply(Om) - Y) / torch.linalg.norm(Y))
+            pw = hbs.power_rel_error(f, A, *_power_starts(inputs, wl["id"], n, torch, dev))
+            return {"rel_apply_err": e, "in_sample_err": ins, "reference": "the exact generator on 8 Gaussian probes",
+                    "power_rel_err": pw, "floats_per_dof": f.floats_per_dof()}
+        return (lambda: f.compress_into(Om, Y, Ps, Z)), f, error
+    P.build = build
 
     def cpu():
-        from oracle import tree as otree
-        levels = otree.cluster_tree(n, leaf)
-        sub = args.cpu_subtree_level + max(0, tree.levels - 10)
-        return cpu_baseline(k, leaf, levels, Om.cpu().numpy(), Y.cpu().numpy(), Ps.cpu().numpy(), Z.cpu().numpy(),
-                            sub, args.workload)
+        # a smaller instance of the same shape, drawn and sampled by the oracle
+        nc = min(n, leaf * 2 ** 10)
+        job = _oracle_synthetic(inputs, nc, k, leaf, s, inputs.streams(wl["id"], extra=(0xC0,)))
+        single = [job] if nc <= leaf * 2 ** 8 else \
+            [_oracle_synthetic(inputs, leaf * 2 ** 8, k, leaf, s, inputs.streams(wl["id"], extra=(0xC1,)))]
+        return cpu_result([job], single, f"oracle Algorithm 2 on an exact-rank instance of {nc} rows with the "
+                                         f"workload's k = {k}, leaf {leaf}, s = {s}, drawn and sampled on the CPU")
     P.cpu = cpu
     return P
 
@@ -243,49 +306,104 @@ def setup_batch(wl, args, hbs, torch, inputs, dev):
     log(f"{len(spec)} generators and samples ready in {time.perf_counter() - t0:.1f} s")
     trees = [i[0] for i in inst]
     Om, Y, Ps, Z = ([i[j] for i in inst] for j in (2, 3, 4, 5))
-    b = hbs.Batch(trees, [x["k"] for x in spec], [x["s"] for x in spec], args.path)
     P = Problem()
     P.sampler_ms = float("nan")
     P.rows = sum(x["n"] for x in spec)
-    P.compress = lambda: b.compress(Om, Y, Ps, Z)
-    P.handle = b.factors(0)
     P.leaf_sets = [(t.leaf_sizes(), x["k"], x["s"]) for t, x in zip(trees, spec)]
     P.config = {"instances": len(spec), "N_total": P.rows, "N_range": [wl["n_lo"], wl["n_hi"]], "k": list(wl["ks"]),
                 "leaf_max": "2k", "s": "3k + 10", "levels": [min(t.levels for t in trees), max(t.levels for t in trees)]}
 
-    def error():
-        worst = 0.0
-        for i, (tree, A, om, yy, ps, zz, G) in enumerate(inst):
-            AG = A.apply(G)
-            worst = max(worst, float(torch.linalg.norm(b.factors(i).apply(G) - AG) / torch.linalg.norm(AG)))
-        i = max(range(len(spec)), key=lambda j: spec[j]["n"])
-        fi = b.factors(i)
-        pw = hbs.power_rel_error(fi, inst[i][1], *_power_starts(inputs, wl["id"], spec[i]["n"], torch, dev))
-        return {"rel_apply_err": worst, "reference": "each instance's exact generator on 8 Gaussian probes (worst)",
-                "power_rel_err": pw, "power_reference": (f"||A~ - A|| / ||A||, 20 power steps each (section 5), "
-                                                         f"largest instance ({spec[i]['n']} rows)"),
-                "floats_per_dof": sum(b.factors(j).floats_per_dof() * spec[j]["n"] for j in range(len(spec))) / P.rows}
-    P.error = error
+    def build(path):
+        b = hbs.Batch(trees, [x["k"] for x in spec], [x["s"] for x in spec], path, args.truncation)
+
+        def error():
+            worst = 0.0
+            for i, (tree, A, om, yy, ps, zz, G) in enumerate(inst):
+                AG = A.apply(G)
+                worst = max(worst, float(torch.linalg.norm(b.factors(i).apply(G) - AG) / torch.linalg.norm(AG)))
+            i = max(range(len(spec)), key=lambda j: spec[j]["n"])
+            pw = hbs.power_rel_error(b.factors(i), inst[i][1], *_power_starts(inputs, wl["id"], spec[i]["n"], torch,
+                                                                                  dev))
+            return {"rel_apply_err": worst, "reference": "each instance's exact generator on 8 Gaussian probes (worst)",
+                    "power_rel_err": pw, "power_reference": f"largest instance ({spec[i]['n']} rows)",
+                    "floats_per_dof": sum(b.factors(j).floats_per_dof() * spec[j]["n"] for j in range(len(spec)))
+                    / P.rows}
+        return (lambda: b.compress(Om, Y, Ps, Z)), b.factors(0), error
+    P.build = build
 
     def cpu():
-        from oracle import tree as otree
-        i = max(range(len(spec)), key=lambda j: spec[j]["n"])
-        tree, A, om, yy, ps, zz, G = inst[i]
-        levels = otree.cluster_tree(spec[i]["n"], spec[i]["leaf_max"])
-        out = cpu_baseline(spec[i]["k"], spec[i]["leaf_max"], levels, om.cpu().numpy(), yy.cpu().numpy(),
-                           ps.cpu().numpy(), zz.cpu().numpy(), 2, f"the largest instance ({spec[i]['n']} rows)")
-        return out
+        # the first 32 instances (multi-threaded) and the first 8 (one thread),
+        # drawn and sampled by the oracle with each instance's own seeds
+        jobs = [_oracle_synthetic(inputs, x["n"], x["k"], x["leaf_max"], x["s"],
+                                  inputs.streams(wl["id"], extra=(x["index"],))) for x in spec[:32]]
+        return cpu_result(jobs, jobs[:8], "oracle Algorithm 2 on the first 32 of the 512 instances, each drawn and "
+                                          "sampled on the CPU from its own seeds (single thread: the first 8)")
     P.cpu = cpu
     return P
+
+
+def run_path(P, path, args, torch):
+    """Warm up, time K sweeps (the captured graph), then K traced sweeps for
+    per-kernel device time; returns the path's figures."""
+    compress, f, error = P.build(path)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(args.warmup):
+        compress()
+    torch.cuda.synchronize()
+    f.check()
+    t0 = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        compress()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = e0.elapsed_time(e1) / args.steps
+    f.check()
+    rows_per_s = P.rows / (ms_per_step / 1e3)
+    log(f"[{path}] {args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms), "
+        f"{rows_per_s:.4g} rows/s")
+    # the same K sweeps launched directly, each launch bracketed by HIP events
+    # on the stream it runs on
+    f.profile(True)
+    f.profile_read()
+    e0.record()
+    for _ in range(args.steps):
+        compress()
+    e1.record()
+    torch.cuda.synchronize()
+    traced_ms = e0.elapsed_time(e1) / args.steps
+    prof = f.profile_read()
+    f.profile(False)
+    f.check()
+    log(f"[{path}] traced {traced_ms:.3f} ms/step; kernel ms/step: " +
+        ", ".join(f"{c} {v[0] / args.steps:.3f} ({v[1] // args.steps} launches)" for c, v in prof.items()))
+    acc = error()
+    log(f"[{path}] accuracy: {acc}")
+    plan = f.plan()
+    tiles = [f"step {p['step']}: {p['boxes']} boxes m<={p['mmax']} lq {p['lq']['threads']}t/{p['lq']['lanes_per_row']}l "
+             f"{p['lq']['test_slots']}x{p['lq']['sample_slots']}x{p['lq']['col_slots']} chunks {p['lq']['chunks']}"
+             + (f" cap {p['lq']['waves_per_simd_cap']}w" if p['lq']['waves_per_simd_cap'] else "")
+             + ("" if p["root"] else f", col {p['col']['threads']}t/{p['col']['lanes_per_row']}l "
+                f"{p['col']['row_slots']}x{p['col']['col_slots']}"
+                + (f" cap {p['col']['waves_per_simd_cap']}w" if p['col']['waves_per_simd_cap'] else "")
+                + f", tail_b {p['tail_b']}")
+             for p in plan]
+    return {"rows_per_s": rows_per_s, "ms_per_step": ms_per_step, "traced_ms_per_step": traced_ms,
+            "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
+            "lq_launches_per_step": prof["lq"][1] / args.steps, **acc,
+            "tiles": {"autotuned": bool(plan and plan[0]["tuned"]), "steps": tiles}}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="logkernel_ellipse_n65536_k50")
-    ap.add_argument("--path", default="fp64", choices=["fp64", "split"])
+    ap.add_argument("--workload", default="hbs_exact_batch512")
+    ap.add_argument("--path", default="both", choices=["both", "fp64", "split"],
+                    help="both: the split-precision path gives `value`, the FP64 path runs beside it")
+    ap.add_argument("--truncation", default="qr", choices=["qr", "svd"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subtree-level", type=int, default=4)
     ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
@@ -296,7 +414,8 @@ def main():
                          "(FETCH_SIZE, WRITE_SIZE) of bench.py --copy-probe MIB into the lq_kernel traffic file")
     args = ap.parse_args()
     if args.traffic_from:
-        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 512, args.workload)
+        traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 512, args.workload,
+                              args=args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -323,117 +442,96 @@ def main():
 
     setup = {"logkernel": setup_logkernel, "synthetic": setup_synthetic, "batch": setup_batch}[wl["kind"]]
     P = setup(wl, args, hbs, torch, inputs, dev)
-    log(f"workload {args.workload}: {P.config}; sampler {P.sampler_ms:.2f} ms; path {args.path}")
-    f = P.handle
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"workload {args.workload}: {P.config}; sampler {P.sampler_ms:.2f} ms; truncation {args.truncation}")
+    paths = ["split", "fp64"] if args.path == "both" else [args.path]
+    res = {p: run_path(P, p, args, torch) for p in paths}
+    head = res[paths[0]]
+    for p in paths:
+        log(f"[{p}] tiles:\n  " + "\n  ".join(res[p]["tiles"]["steps"]))
 
-    # ---- warmup, then K timed sweeps (the captured graph, as callers run it)
-    for _ in range(args.warmup):
-        P.compress()
-    torch.cuda.synchronize()
-    f.check()
-    t0 = time.perf_counter()
-    e0.record()
-    for _ in range(args.steps):
-        P.compress()
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    f.check()
-    ms_per_step = gpu_ms / args.steps
-    rows_per_s = P.rows / (ms_per_step / 1e3)
-    log(f"{args.steps} steps: {ms_per_step:.3f} ms/step (wall {wall * 1e3 / args.steps:.3f} ms), "
-        f"{rows_per_s:.4g} rows/s")
-
-    # ---- per-kernel device time: the same K sweeps launched directly, each
-    # launch bracketed by HIP events on the stream it runs on
-    f.profile(True)
-    f.profile_read()
-    e0.record()
-    for _ in range(args.steps):
-        P.compress()
-    e1.record()
-    torch.cuda.synchronize()
-    traced_ms = e0.elapsed_time(e1) / args.steps
-    prof = f.profile_read()
-    f.profile(False)
-    f.check()
-    log(f"traced pass {traced_ms:.3f} ms/step; kernel ms/step: " +
-        ", ".join(f"{c} {v[0] / args.steps:.3f} ({v[1] // args.steps} launches)" for c, v in prof.items()))
-
-    acc = P.error()
-    log(f"accuracy: {acc}")
-    plan = f.plan()
-    tiles = [f"step {p['step']}: {p['boxes']} boxes m<={p['mmax']} lq {p['lq']['threads']}t/{p['lq']['lanes_per_row']}l "
-             f"{p['lq']['test_slots']}x{p['lq']['sample_slots']}x{p['lq']['col_slots']} chunks {p['lq']['chunks']}"
-             + (f" cap {p['lq']['waves_per_simd_cap']}w" if p['lq']['waves_per_simd_cap'] else "")
-             + ("" if p["root"] else f", col {p['col']['threads']}t/{p['col']['lanes_per_row']}l "
-                f"{p['col']['row_slots']}x{p['col']['col_slots']}"
-                + (f" cap {p['col']['waves_per_simd_cap']}w" if p['col']['waves_per_simd_cap'] else "")
-                + f", tail_b {p['tail_b']}")
-             for p in plan]
-    log(("autotuned" if plan and plan[0]["tuned"] else "heuristic") + " tiles:\n  " + "\n  ".join(tiles))
-
-    # ---- roofline of the dominant kernel (the QR kernel, lq_kernel) ----------
-    model = {"lq": 0.0, "col": 0.0, "tail": 0.0, "root": 0.0, "lq_bytes": 0.0}
+    # ---- roofline of the dominant kernel (the QR kernel, FP64 on both paths)
+    model = {"lq": 0.0, "col": 0.0, "tail": 0.0, "root": 0.0, "lq_bytes": 0.0, "nominal": 0.0, "nominal_lq": 0.0}
     for leaf_sizes, k, s in P.leaf_sets:
         mdl = sweep_model(leaf_sizes, k, s)
         for c in model:
             model[c] += mdl[c]
-    lq_ms, lq_launches = prof["lq"][0] / args.steps, prof["lq"][1] / args.steps
+    lq_ms, lq_launches = head["kernel_ms_per_step"]["lq"], head["lq_launches_per_step"]
     avg_launch_ms = lq_ms / lq_launches
-    per_launch = model["lq"] / lq_launches
+    per_launch = model["nominal_lq"] / lq_launches
     achieved = per_launch / (avg_launch_ms / 1e3) / 1e12
+    own = model["lq"] / lq_launches / (avg_launch_ms / 1e3) / 1e12
     traffic = None
     tfile = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                          f"lq_kernel_{args.workload}_traffic.json")
-    if os.path.exists(tfile) and args.path == "fp64":
+    if os.path.exists(tfile):
         with open(tfile) as fh:
             tr = json.load(fh)
         if tr.get("source_digest") == _side_digest():
             traffic = tr.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP64_TFLOPS, 1),
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
-                "kernel": "lq_kernel", "flops_per_launch": per_launch, "avg_launch_ms": avg_launch_ms,
+                "kernel": "lq_kernel", "flop_model": "nominal (literal Algorithm 2, LAPACK counts)",
+                "flops_per_launch": per_launch, "avg_launch_ms": avg_launch_ms,
+                "own_model_achieved": round(own, 3), "own_model_frac": round(own / PEAK_FP64_TFLOPS, 4),
                 "algorithmic_hbm_bytes_per_launch": model["lq_bytes"] / lq_launches}
-    total_flops = sum(model[c] for c in ("lq", "col", "tail", "root"))
 
+    def strip(r):
+        return {k: v for k, v in r.items() if k not in ("tiles", "lq_launches_per_step")}
     out = {
-        "metric": METRIC, "value": rows_per_s, "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if args.path == "fp64" else "f64+i8-slices", "data": "synthetic",
-        "config": {"workload": args.workload, **P.config, "path": args.path},
+        "metric": METRIC, "value": head["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64+i8-slices" if paths[0] == "split" else "f64", "data": "synthetic",
+        "config": {"workload": args.workload, **P.config, "path": paths[0], "truncation": args.truncation},
         "roofline": roofline,
-        **acc,
-        "sampler_ms": P.sampler_ms, "rows_per_s_incl_sampler": P.rows / ((ms_per_step + P.sampler_ms) / 1e3),
-        "sweep_tflops_model": total_flops / (ms_per_step / 1e3) / 1e12,
-        "traced_ms_per_step": traced_ms,
-        "kernel_ms_per_step": {c: v[0] / args.steps for c, v in prof.items()},
-        "tiles": {"autotuned": bool(plan and plan[0]["tuned"]), "steps": tiles},
+        "rel_apply_err": head["rel_apply_err"], "power_rel_err": head["power_rel_err"],
+        "paths": {p: strip(res[p]) for p in paths},
+        "sampler_ms": P.sampler_ms,
+        "sweep_tflops_nominal": model["nominal"] / (head["ms_per_step"] / 1e3) / 1e12,
+        "tiles": res[paths[0]]["tiles"],
     }
+    if len(paths) == 2:
+        out["mixed_vs_fp64_speedup"] = res["fp64"]["ms_per_step"] / res["split"]["ms_per_step"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = P.cpu()
-        log(f"cpu baseline: {out['cpu_baseline']['value']:.4g} rows/s on {out['cpu_baseline']['cores']} threads")
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 
-def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None):
-    """HBM bytes per lq_kernel launch from two rocprofv3 --pmc passes of
-    `bench.py --copy-probe MIB` (FETCH_SIZE, then WRITE_SIZE, in KiB per
-    dispatch).  Each counter is scaled by what it reads for the plain MIB MiB
-    copy of the same run; the per-level bytes average the last six sweeps
-    (after the autotuner's timing launches), each sweep's root launch left
-    out, matching the launches the roofline's time covers.  Written, with the
-    digest of the QR kernel's source, to the profiles file bench.py reads."""
-    import csv
+def lq_launch_roots(workload):
+    """Whether each QR-kernel launch of one sweep is a root launch, in launch
+    order (host arithmetic on the trees, no GPU): one launch per aligned
+    level and (k, s) class, the roots last."""
+    import inputs
 
     from paper_2205_02990_amd import hbs
 
     wl = inputs_workloads()[workload]
-    if wl["kind"] == "batch":
-        raise SystemExit("per-level traffic is summarised for single-instance workloads")
-    per = hbs.Tree(wl["n"], wl["leaf_max"]).levels + 1  # lq launches per sweep: the levels, then the root
+    if wl["kind"] != "batch":
+        return [False] * hbs.Tree(wl["n"], wl["leaf_max"]).levels + [True]
+    spec = inputs.batch_instances(wl["id"], wl["count"], wl["n_lo"], wl["n_hi"], wl["ks"])
+    L = [hbs.Tree(x["n"], x["leaf_max"]).levels for x in spec]
+    classes = sorted({(x["k"], x["s"]) for x in spec})
+    maxL = max(L)
+    roots = []
+    for j in range(maxL + 1):
+        for c in classes:
+            if j == maxL or any(Li > j for Li, x in zip(L, spec) if (x["k"], x["s"]) == c):
+                roots.append(j == maxL)
+    return roots
+
+
+def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None, args=None):
+    """HBM bytes per lq_kernel launch from two rocprofv3 --pmc passes of
+    `bench.py --copy-probe MIB` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch).  Each counter is scaled by what it reads for the plain MIB MiB
+    copy of the same run; the bytes average the last six sweeps (after the
+    autotuner's timing launches), each sweep's root launches left out,
+    matching the launches the roofline's time covers.  Written, with the
+    digest of the QR kernel's source, to the profiles file bench.py reads."""
+    import csv
+
+    roots = lq_launch_roots(workload)
+    per = len(roots)
     res = {}
     for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
         with open(path) as fh:
@@ -444,10 +542,15 @@ def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None):
         scale = mib * 1024.0 / (sum(copy) / len(copy))
         lq = [r for r in rows if "lq_kernel" in r["Kernel_Name"]][-6 * per:]
         sweeps = [lq[i:i + per] for i in range(0, len(lq) - len(lq) % per, per)]
-        vals = [[float(r["Counter_Value"]) * scale * 1024 for r in sw[:-1]] for sw in sweeps]
+        vals = [[float(r["Counter_Value"]) * scale * 1024 for r, root in zip(sw, roots) if not root]
+                for sw in sweeps]
+        nl = len(vals[0])
         res[name] = dict(scale=scale, copy_kib=copy[0],
-                         per_level=[sum(v[i] for v in vals) / len(vals) for i in range(per - 1)])
-    fetch, write = res["FETCH_SIZE"]["per_level"], res["WRITE_SIZE"]["per_level"]
+                         per_launch=[sum(v[i] for v in vals) / len(vals) for i in range(nl)])
+    fetch, write = res["FETCH_SIZE"]["per_launch"], res["WRITE_SIZE"]["per_launch"]
+    extra = ""
+    if args is not None:
+        extra = (f" --workload {workload} --path {args.path} --truncation {args.truncation}")
     out = {"kernel": "lq_kernel", "workload": workload,
            "bytes_per_launch": (sum(fetch) + sum(write)) / len(fetch),
            "fetch_bytes_per_level": fetch, "write_bytes_per_level": write,
@@ -456,8 +559,7 @@ def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None):
                           f"WRITE_SIZE {res['WRITE_SIZE']['copy_kib']:.0f} KiB per dispatch",
            "source_digest": _side_digest(),
            "command": "rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE) -f csv -d <dir> -o run -- python3 -u bench.py "
-                      f"--steps 3 --warmup 1 --no-cpu-baseline --copy-probe {mib}" +
-                      ("" if workload == "logkernel_ellipse_n65536_k50" else f" --workload {workload}")}
+                      f"--steps 3 --warmup 1 --no-cpu-baseline --copy-probe {mib}" + extra}
     if dst is None:
         dst = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", f"lq_kernel_{workload}_traffic.json")
     with open(dst, "w") as fh:

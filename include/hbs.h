@@ -54,6 +54,28 @@ typedef enum {
                            * FP32 sums                                         */
 } hbs_precision;
 
+/* How col(B, k) of section 2.4 truncates the whole-nullspace sketch
+ * B = Y_tau P_tau (m_tau x (s - m_tau)) to its k basis columns.  Given by
+ * OR-ing one of these into the precision argument of hbs_factors_create,
+ * hbs_compress, hbs_batch_create and hbs_compress_batched (HBS_TRUNC_QR
+ * when none is given):
+ *   HBS_TRUNC_QR   the truncated QR named in section 2.4: Householder QR
+ *                  with column pivoting (largest remaining column first),
+ *                  stopped after k steps; the k columns of Q it produced.
+ *   HBS_TRUNC_SVD  the k leading left singular vectors of B (largest
+ *                  singular value first), the truncation that minimises
+ *                  ||B - Q Q^* B|| (section 2.3's goal).  Computed as the
+ *                  pivoted QR run to min(m_tau, s - m_tau) steps, then
+ *                  one-sided Jacobi on the triangular factor (at most 3
+ *                  sweeps; HBS_JACOBI_SWEEPS in the environment at create
+ *                  time sets another cap, 1..20).  The basis depends only on
+ *                  B B^*, and rounding errors no longer grow from level to
+ *                  level through the choice of k sketch columns. */
+typedef enum {
+  HBS_TRUNC_QR = 0,
+  HBS_TRUNC_SVD = 0x100
+} hbs_truncation;
+
 typedef struct hbs_tree hbs_tree;        /* host-only, immutable after create */
 typedef struct hbs_factors hbs_factors;  /* owns device memory                */
 typedef struct hbs_batch hbs_batch;      /* owns device memory of many sets  */
@@ -90,7 +112,10 @@ typedef struct {
  * N x N matrix on tree `t` with bases of width k from s samples.  Every box
  * tau needs m_tau >= k and s - m_tau >= k (the nullspace of its m_tau x s test
  * matrix must hold a k-column sketch); the root needs s >= its row count (2k,
- * or N when L = 0).  `prec` selects the arithmetic of the bulk products.
+ * or N when L = 0).  `prec` selects the arithmetic of the bulk products,
+ * optionally OR-ed with an hbs_truncation; unknown bits are HBS_EINVAL.
+ * HBS_FP32_SPLIT needs every box to have at most 128 rows (largest leaf,
+ * and 2k above the leaves), else HBS_EUNSUPPORTED.
  * Device memory is allocated here, once; hbs_compress_into calls no
  * hipMalloc (its first call captures the sweep as a HIP graph, later calls
  * replay it). */
@@ -103,12 +128,16 @@ void       hbs_factors_destroy(hbs_factors* f);
  * build the telescoping factorization of A into `f`.  For every box of a
  * level at once: the full Householder QR of Omega_tau^* gives the nullspace
  * P_tau (its trailing s - m_tau columns, section 2.4) and Omega_tau^dagger;
- * U_tau = col(Y_tau P_tau, k) by column-pivoted truncated QR (eqs.
- * u_tau_formula, v_tau_formula); D_tau by eq. d_tau_formula; then the
+ * U_tau = col(Y_tau P_tau, k) truncated as the factor set's hbs_truncation
+ * says (eqs. u_tau_formula, v_tau_formula); D_tau by eq. d_tau_formula; then the
  * reduced test and sample matrices of eq. omega_tau_and_y_tau feed the next
  * level up; the root block is D^(0) = Y_root Omega_root^dagger.  The previous
  * contents of `f` are overwritten.  The first call on a factor set also
- * autotunes the tiles (see hbs_sweep_plan) and waits for the stream. */
+ * autotunes the tiles (see hbs_sweep_plan) and waits for the stream.
+ * Ordering: the input pointers are captured at the call (a later call may
+ * pass other inputs before this one has run), and every call on a factor
+ * set or batch (compress, apply, import) runs after the previous one on the
+ * device, also when they are made on different streams. */
 hbs_status hbs_compress_into(hbs_factors* f, const double* Omega, const double* Y, const double* Psi,
                              const double* Z, int64_t ld, void* hip_stream);
 

@@ -71,7 +71,8 @@ struct Launch {
   hbs::SweepArgs args;
   // tile choices (heuristic until the autotuner has run)
   hbs::LqChoice lq{-1, 0};
-  int col = -1;
+  int col = -1;    // tile of the basis kernel (mode 0, or mode 1 for the SVD truncation)
+  int colj = -1;   // SVD truncation: tile of the Jacobi pass (mode 2)
   int tailb = -1;
 };
 
@@ -87,10 +88,26 @@ struct Mark {
 struct BatchImpl {
   std::vector<Instance> inst;
   hbs_precision prec = HBS_FP64;
+  bool svd = false;       // bases by SVD truncation of the sketches (else truncated pivoted QR)
+  int jac_sweeps = 3;     // SVD truncation: most Jacobi sweeps per sketch
   std::vector<void*> allocs;
-  hbs::PanelSrc* h_src = nullptr;  // pinned host copy of the panel-source table
+  // The panel-source table: the host template (callers' inputs are written
+  // into it), and a ring of pinned copies, one per call, each reused only
+  // after the event recorded behind its upload has completed, so that a
+  // later call never rewrites the bytes an earlier call's copy still reads.
+  std::vector<hbs::PanelSrc> h_src;
+  static constexpr int kStage = 4;
+  hbs::PanelSrc* h_stage[kStage] = {};
+  hipEvent_t stage_ev[kStage] = {};
+  bool stage_used[kStage] = {};
+  int stage_next = 0;
   hbs::PanelSrc* d_src = nullptr;
   int nsrc = 0;
+  // Every call on the batch (sweep or apply) records this event behind its
+  // work; a call on another stream first waits for it, so calls on one
+  // batch never overlap on the device (they share the workspace).
+  hipEvent_t done_ev = nullptr;
+  bool done_rec = false;
   hbs::BoxDesc* d_box = nullptr;
   std::vector<Launch> launches;
   int32_t* flag = nullptr;
@@ -145,10 +162,30 @@ struct BatchImpl {
       (void)hipEventDestroy(m.a);
       (void)hipEventDestroy(m.b);
     }
-    if (h_src) (void)hipHostFree(h_src);
+    for (int i = 0; i < kStage; ++i) {
+      if (h_stage[i]) (void)hipHostFree(h_stage[i]);
+      if (stage_ev[i]) (void)hipEventDestroy(stage_ev[i]);
+    }
+    if (done_ev) (void)hipEventDestroy(done_ev);
     for (void* p : allocs) (void)hipFree(p);
   }
 };
+
+namespace {
+
+// Order a call on stream st after the batch's previous call (any stream).
+hipError_t batch_enter(BatchImpl* b, hipStream_t st) {
+  if (b->done_rec && st != b->last) return hipStreamWaitEvent(st, b->done_ev, 0);
+  return hipSuccess;
+}
+hipError_t batch_leave(BatchImpl* b, hipStream_t st) {
+  b->last = st;
+  hipError_t e = hipEventRecord(b->done_ev, st);
+  if (e == hipSuccess) b->done_rec = true;
+  return e;
+}
+
+}  // namespace
 
 // The caller's batch handle: one more owner of the shared storage.
 struct hbs_batch {
@@ -164,12 +201,15 @@ struct hbs_factors {
 
 namespace {
 
-hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
+hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s, bool mixed, bool svd) {
   if (!t || k < 1 || s < 1) return HBS_EINVAL;
+  // the tiles' spill facts are read before any shape is judged (without a
+  // device they stay unknown; the factor set's own set-up then fails)
+  (void)hbs::prepare_side_kernels();
   const int L = t->L;
   if (L == 0) {
     if (s < t->n) return HBS_EINVAL;
-    if (!hbs::side_supported((int)t->n, (int)t->n, s, k, true)) return HBS_EUNSUPPORTED;
+    if (!hbs::side_supported((int)t->n, (int)t->n, s, k, true, svd)) return HBS_EUNSUPPORTED;
     return HBS_OK;
   }
   int64_t mmin = INT64_MAX, mmax = 0;
@@ -181,9 +221,12 @@ hbs_status check_shape(const hbs_tree* t, int32_t k, int32_t s) {
   if (mmin < k || s - mmax < k) return HBS_EINVAL;        // leaves
   if (L > 1 && s - 2 * (int64_t)k < k) return HBS_EINVAL;  // inner boxes of 2k rows
   if (s < 2 * (int64_t)k) return HBS_EINVAL;               // root
-  if (!hbs::side_supported((int)mmin, (int)mmax, s, k, false)) return HBS_EUNSUPPORTED;
-  if (L > 1 && !hbs::side_supported(2 * k, 2 * k, s, k, false)) return HBS_EUNSUPPORTED;
-  if (!hbs::side_supported(2 * k, 2 * k, s, k, true)) return HBS_EUNSUPPORTED;
+  if (!hbs::side_supported((int)mmin, (int)mmax, s, k, false, svd)) return HBS_EUNSUPPORTED;
+  if (L > 1 && !hbs::side_supported(2 * k, 2 * k, s, k, false, svd)) return HBS_EUNSUPPORTED;
+  if (!hbs::side_supported(2 * k, 2 * k, s, k, true, svd)) return HBS_EUNSUPPORTED;
+  // the split products contract over at most tail_mixed_max_rows() box rows
+  if (mixed && std::max<int64_t>(mmax, L > 1 ? 2 * (int64_t)k : 0) > hbs::tail_mixed_max_rows())
+    return HBS_EUNSUPPORTED;
   return HBS_OK;
 }
 
@@ -251,8 +294,11 @@ hbs_status build_sweep(BatchImpl* b) {
     for (int l = 0; l < in.L; ++l) in.src_lev[l] = nsrc++;
   }
   b->nsrc = nsrc;
-  HIP_TRY(hipHostMalloc((void**)&b->h_src, sizeof(hbs::PanelSrc) * nsrc, hipHostMallocDefault));
-  std::memset(b->h_src, 0, sizeof(hbs::PanelSrc) * nsrc);
+  b->h_src.assign(nsrc, hbs::PanelSrc{});
+  for (int i = 0; i < BatchImpl::kStage; ++i) {
+    HIP_TRY(hipHostMalloc((void**)&b->h_stage[i], sizeof(hbs::PanelSrc) * nsrc, hipHostMallocDefault));
+    HIP_TRY(hipEventCreateWithFlags(&b->stage_ev[i], hipEventDisableTiming));
+  }
   for (Instance& in : b->inst)
     for (int l = 0; l < in.L; ++l)
       b->h_src[in.src_lev[l]] = hbs::PanelSrc{{in.lev[l].bOm, in.lev[l].bY, in.lev[l].bPs, in.lev[l].bZ}, in.s};
@@ -357,6 +403,8 @@ hbs_status build_sweep(BatchImpl* b) {
       ln.args.mmin = mmin;
       ln.args.root = g.root ? 1 : 0;
       ln.args.mixed = b->prec == HBS_FP32_SPLIT ? 1 : 0;
+      ln.args.svd = b->svd ? 1 : 0;
+      ln.args.jac_sweeps = b->jac_sweeps;
       ln.args.flag = b->flag;
       b->launches.push_back(ln);
     }
@@ -373,7 +421,8 @@ hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
     HIP_TRY(b->mark_end(st));
     if (ln.args.root) continue;
     HIP_TRY(b->mark_begin(1, st));
-    HIP_TRY(hbs::launch_col(ln.args, ln.col, st));
+    HIP_TRY(hbs::launch_col(ln.args, ln.args.svd ? 1 : 0, ln.col, st));
+    if (ln.args.svd) HIP_TRY(hbs::launch_col(ln.args, 2, ln.colj, st));
     HIP_TRY(b->mark_end(st));
     for (int part = 0; part < 3; ++part) {
       HIP_TRY(b->mark_begin(2 + part, st));
@@ -393,17 +442,18 @@ hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
 // device and launch shape for the life of the process, so later batches of
 // the same shapes reuse them without timing.
 struct TuneKey {
-  int dev, kind, mmax, mmin, s, k, nboxes, mixed, root;
+  int dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps;
   bool operator<(const TuneKey& o) const {
-    return std::tie(dev, kind, mmax, mmin, s, k, nboxes, mixed, root) <
-           std::tie(o.dev, o.kind, o.mmax, o.mmin, o.s, o.k, o.nboxes, o.mixed, o.root);
+    return std::tie(dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps) <
+           std::tie(o.dev, o.kind, o.mmax, o.mmin, o.s, o.k, o.nboxes, o.mixed, o.root, o.svd, o.sweeps);
   }
 };
 std::mutex g_tune_mu;
-std::map<TuneKey, std::pair<int, int>> g_tune;  // kind 0: (lq cfg, ns); 1: (col cfg, 0); 2: (tail_b variant, 0)
+std::map<TuneKey, std::pair<int, int>> g_tune;  // kind 0: (lq cfg, ns); 1: (col cfg, 0); 2: (tail_b variant, 0);
+                                                // 3: (Jacobi-pass col cfg, 0)
 
 TuneKey tune_key(int dev, int kind, const hbs::SweepArgs& a) {
-  return TuneKey{dev, kind, a.mmax, a.mmin, a.s, a.k, a.nboxes, a.mixed, a.root};
+  return TuneKey{dev, kind, a.mmax, a.mmin, a.s, a.k, a.nboxes, a.mixed, a.root, a.svd, a.svd ? a.jac_sweeps : 0};
 }
 
 bool tune_lookup(const TuneKey& key, std::pair<int, int>* v) {
@@ -464,21 +514,40 @@ hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
     }
     if (e == hipSuccess) e = hbs::launch_lq(a, ln.lq, st);
     if (e != hipSuccess || a.root) continue;
-    // truncated pivoted QR
+    // the bases: truncated pivoted QR (and, for the SVD truncation, its
+    // first-order correction, then the Jacobi pass over the flagged boxes)
+    const int cmode = a.svd ? 1 : 0;
     if (tune_lookup(tune_key(dev, 1, a), &v)) {
       ln.col = v.first;
     } else {
       int cand[16];
-      const int n = hbs::col_candidates(a, cand, 16);
+      const int n = hbs::col_candidates(a, cmode, cand, 16);
       float best = 1e30f;
       for (int i = 0; i < n && e == hipSuccess; ++i) {
         float t = 0.0f;
-        e = time_twice([&] { return hbs::launch_col(a, cand[i], st); }, e0, e1, st, &t);
+        e = time_twice([&] { return hbs::launch_col(a, cmode, cand[i], st); }, e0, e1, st, &t);
         if (e == hipSuccess && t < best) best = t, ln.col = cand[i];
       }
       if (e == hipSuccess && ln.col >= 0) tune_store(tune_key(dev, 1, a), {ln.col, 0});
     }
-    if (e == hipSuccess) e = hbs::launch_col(a, ln.col, st);
+    if (e == hipSuccess) e = hbs::launch_col(a, cmode, ln.col, st);
+    if (a.svd && e == hipSuccess) {
+      // (timed on this data: the flags the pass above left behind)
+      if (tune_lookup(tune_key(dev, 3, a), &v)) {
+        ln.colj = v.first;
+      } else {
+        int cand[16];
+        const int n = hbs::col_candidates(a, 2, cand, 16);
+        float best = 1e30f;
+        for (int i = 0; i < n && e == hipSuccess; ++i) {
+          float t = 0.0f;
+          e = time_twice([&] { return hbs::launch_col(a, 2, cand[i], st); }, e0, e1, st, &t);
+          if (e == hipSuccess && t < best) best = t, ln.colj = cand[i];
+        }
+        if (e == hipSuccess && ln.colj >= 0) tune_store(tune_key(dev, 3, a), {ln.colj, 0});
+      }
+      if (e == hipSuccess) e = hbs::launch_col(a, 2, ln.colj, st);
+    }
     if (e == hipSuccess) e = hbs::launch_tail(a, 0, -1, st);
     // the k-wide terms
     if (e == hipSuccess && tune_lookup(tune_key(dev, 2, a), &v)) {
@@ -501,10 +570,28 @@ hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
   return e;
 }
 
+hbs_status run_sweep_body(BatchImpl* b, hipStream_t st);
+
 // Point the panel-source slots at the caller's inputs, then run the sweep:
 // replay of the captured graph, or direct launches while tracing.
 hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(b->d_src, b->h_src, sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st));
+  HIP_TRY(batch_enter(b, st));
+  {
+    const int i = b->stage_next;
+    b->stage_next = (i + 1) % BatchImpl::kStage;
+    if (b->stage_used[i]) HIP_TRY(hipEventSynchronize(b->stage_ev[i]));  // its earlier upload has run
+    std::memcpy(b->h_stage[i], b->h_src.data(), sizeof(hbs::PanelSrc) * b->nsrc);
+    HIP_TRY(hipMemcpyAsync(b->d_src, b->h_stage[i], sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipEventRecord(b->stage_ev[i], st));
+    b->stage_used[i] = true;
+  }
+  hbs_status res = run_sweep_body(b, st);
+  if (res != HBS_OK) return res;
+  HIP_TRY(batch_leave(b, st));
+  return HBS_OK;
+}
+
+hbs_status run_sweep_body(BatchImpl* b, hipStream_t st) {
   b->last = st;
   if (b->autotune && !b->tuned) {
     // the first sweep picks the tiles; the sweep below (graph capture or
@@ -537,10 +624,14 @@ hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
 hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t* k, const int32_t* s,
                       hbs_precision prec, bool with_sweep, std::shared_ptr<BatchImpl>* out) {
   if (count < 1 || !trees || !k || (with_sweep && !s)) return HBS_EINVAL;
-  if (prec != HBS_FP64 && prec != HBS_FP32_SPLIT) return HBS_EUNSUPPORTED;
+  const int pflags = (int)prec;
+  if (pflags & ~(0xff | HBS_TRUNC_SVD)) return HBS_EINVAL;
+  const bool svd = (pflags & HBS_TRUNC_SVD) != 0;
+  const hbs_precision pbase = (hbs_precision)(pflags & 0xff);
+  if (pbase != HBS_FP64 && pbase != HBS_FP32_SPLIT) return HBS_EUNSUPPORTED;
   for (int i = 0; i < count; ++i) {
     if (with_sweep) {
-      hbs_status st = check_shape(trees[i], k[i], s[i]);
+      hbs_status st = check_shape(trees[i], k[i], s[i], pbase == HBS_FP32_SPLIT, svd);
       if (st != HBS_OK) return st;
     } else if (!trees[i] || k[i] < 1) {
       return HBS_EINVAL;
@@ -548,13 +639,17 @@ hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t
   }
   std::shared_ptr<BatchImpl> b(new (std::nothrow) BatchImpl);
   if (!b) return HBS_ENOMEM;
-  b->prec = prec;
+  b->prec = pbase;
+  b->svd = svd;
   {
     const char* ev = std::getenv("HBS_AUTOTUNE");  // "0": keep the built-in tile heuristic
     b->autotune = !(ev && ev[0] == '0');
+    const char* js = std::getenv("HBS_JACOBI_SWEEPS");  // most Jacobi sweeps of the SVD truncation
+    if (js) b->jac_sweeps = std::max(1, std::min(20, std::atoi(js)));
   }
   HIP_TRY(b->alloc((void**)&b->flag, sizeof(int32_t)));
   HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));
+  HIP_TRY(hipEventCreateWithFlags(&b->done_ev, hipEventDisableTiming));
   b->inst.resize(count);
   for (int i = 0; i < count; ++i) {
     Instance& in = b->inst[i];
@@ -573,6 +668,9 @@ hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t
 }
 
 Instance& inst_of(const hbs_factors* f) { return f->b->inst[f->idx]; }
+
+hbs_status apply_body(hbs_factors* f, int transpose, const double* Xin, double* Out, int64_t nvec, int64_t ldx,
+                      double* qhat, double* uhat, hipStream_t st);
 
 
 }  // namespace
@@ -757,17 +855,12 @@ hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* O
                      void* hip_stream) {
   if (!f || !Xin || !Out || nvec < 1 || ldx < nvec) return HBS_EINVAL;
   hipStream_t st = (hipStream_t)hip_stream;
+  BatchImpl* b = f->b.get();
   Instance& in = inst_of(f);
-  f->b->last = st;
-  const int L = in.L, k = in.k;
-  if (L == 0) {
-    HIP_TRY(hbs::launch_dense_small(in.D0, in.n0, transpose ? 1 : 0, Xin, ldx, Out, ldx, in.n0, (int)nvec, in.n0,
-                                    st));
-    return HBS_OK;
-  }
-  if (nvec > in.apply_nvec) {
+  HIP_TRY(batch_enter(b, st));
+  if (in.L > 0 && nvec > in.apply_nvec) {
     HIP_TRY(hipStreamSynchronize(st));
-    const size_t rows = (size_t)in.hoff[L + 1];
+    const size_t rows = (size_t)in.hoff[in.L + 1];
     void* q = nullptr;
     void* u = nullptr;
     f->b->release(in.qhat);
@@ -780,8 +873,29 @@ hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* O
     in.uhat = (double*)u;
     in.apply_nvec = nvec;
   }
-  auto qh = [&](int l) { return in.qhat + in.hoff[l] * nvec; };
-  auto uh = [&](int l) { return in.uhat + in.hoff[l] * nvec; };
+  hbs_status res = apply_body(f, transpose, Xin, Out, nvec, ldx, in.qhat, in.uhat, st);
+  if (res != HBS_OK) return res;
+  HIP_TRY(batch_leave(b, st));
+  return HBS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Algorithm 1 with the level blocks q-hat and u-hat (hoff[L + 1] x nvec
+// doubles each) in the given device buffers.
+hbs_status apply_body(hbs_factors* f, int transpose, const double* Xin, double* Out, int64_t nvec, int64_t ldx,
+                      double* qhat, double* uhat, hipStream_t st) {
+  Instance& in = inst_of(f);
+  const int L = in.L, k = in.k;
+  if (L == 0) {
+    HIP_TRY(hbs::launch_dense_small(in.D0, in.n0, transpose ? 1 : 0, Xin, ldx, Out, ldx, in.n0, (int)nvec, in.n0,
+                                    st));
+    return HBS_OK;
+  }
+  auto qh = [&](int l) { return qhat + in.hoff[l] * nvec; };
+  auto uh = [&](int l) { return uhat + in.hoff[l] * nvec; };
   // upward pass
   for (int l = L; l >= 1; --l) {
     Level& lv = in.lev[l];
@@ -828,6 +942,10 @@ hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* O
   return HBS_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
 hbs_status hbs_factors_import(const hbs_tree* t, int32_t k, const hbs_level_view* levels, const double* D0,
                               void* hip_stream, hbs_factors** out) {
   if (!out) return HBS_EINVAL;
@@ -839,6 +957,7 @@ hbs_status hbs_factors_import(const hbs_tree* t, int32_t k, const hbs_level_view
   if (st != HBS_OK) return st;
   Instance& in = b->inst[0];
   hipStream_t hs = (hipStream_t)hip_stream;
+  HIP_TRY(batch_enter(b.get(), hs));
   for (int l = 1; l <= in.L; ++l) {
     const hbs_level_view& v = levels[l - 1];
     Level& lv = in.lev[l];
@@ -851,7 +970,7 @@ hbs_status hbs_factors_import(const hbs_tree* t, int32_t k, const hbs_level_view
     HIP_TRY(hipMemcpyAsync(lv.D, v.D, nd, hipMemcpyDeviceToDevice, hs));
   }
   HIP_TRY(hipMemcpyAsync(in.D0, D0, sizeof(double) * (size_t)in.n0 * in.n0, hipMemcpyDeviceToDevice, hs));
-  b->last = hs;
+  HIP_TRY(batch_leave(b.get(), hs));
   hbs_factors* f = new (std::nothrow) hbs_factors;
   if (!f) return HBS_ENOMEM;
   f->b = b;
@@ -900,9 +1019,10 @@ hbs_status hbs_sweep_plan(const hbs_factors* f, int32_t* rows, int32_t max_rows,
     for (int c = 0; c < 6; ++c) r[7 + c] = v[c];
     r[18] = v[6];
     if (!a.root) {
-      const int col = ln.col >= 0 ? ln.col : hbs::col_default(a);
+      const int cmode = a.svd ? 1 : 0;
+      const int col = ln.col >= 0 ? ln.col : hbs::col_default(a, cmode);
       int w[5] = {0, 0, 0, 0, 0};
-      if (col >= 0) hbs::col_describe(col, w);
+      if (col >= 0) hbs::col_describe(cmode, col, w);
       for (int c = 0; c < 4; ++c) r[13 + c] = w[c];
       r[19] = w[4];
       r[17] = ln.tailb >= 0 ? ln.tailb : (a.nboxes < 256 ? 1 : 0);

@@ -42,6 +42,8 @@ struct SweepArgs {
   int32_t nboxes, k, s, mmax, mmin;
   int32_t root;   // 1: only W = Y Omega^dagger of each box (written to D)
   int32_t mixed;  // 1: split-precision bulk products in the tail kernels
+  int32_t svd;    // 1: bases by SVD truncation of the sketch, 0: truncated pivoted QR
+  int32_t jac_sweeps;  // SVD truncation: most Jacobi sweeps per sketch
   int32_t* flag;
 };
 
@@ -63,7 +65,7 @@ struct ApplyArgs {
   int32_t leaf;          // 1: rows addressed through row0 (finest level)
 };
 
-bool side_supported(int mmin, int mmax, int s, int k, bool root);
+bool side_supported(int mmin, int mmax, int s, int k, bool root, bool svd);
 hipError_t prepare_side_kernels();
 // Launch choices the autotuner picks among: a QR tile class (index into the
 // compiled classes) with a number of sample-row chunks per box; cfg < 0 means
@@ -75,23 +77,27 @@ struct LqChoice {
 // shape of a choice (lq: nt, cpr, ra, rs, cpl, ns, register cap in waves per
 // SIMD or 0; col: nt, cpr, rpl, cpl, register cap).
 int lq_candidates(const SweepArgs& a, LqChoice* out, int max);
-int col_candidates(const SweepArgs& a, int* out, int max);
+// col modes: 0 truncated pivoted QR; for the SVD truncation, 1 its
+// first-order correction (every box) then 2 Jacobi (boxes mode 1 flagged)
+int col_candidates(const SweepArgs& a, int mode, int* out, int max);
 LqChoice lq_default(const SweepArgs& a);
-int col_default(const SweepArgs& a);
+int col_default(const SweepArgs& a, int mode);
 void lq_describe(LqChoice c, int* v);
-void col_describe(int c, int* v);
+void col_describe(int mode, int c, int* v);
 // QR of the test blocks, reflectors applied to the samples, Y Omega^dagger
 // (both sides of every box; the root's one side)
 hipError_t launch_lq(const SweepArgs& a, LqChoice ch, hipStream_t st);
 // N of a factor set's tree (host)
 int64_t factors_n(const hbs_factors* f);
-// truncated column-pivoted QR of the nullspace sketches: U_tau, V_tau
-// (cfg: index of a column tile class, < 0 for the heuristic)
-hipError_t launch_col(const SweepArgs& a, int cfg, hipStream_t st);
+// the bases U_tau, V_tau from the nullspace sketches, kernel mode as above
+// (cfg: index of a column tile class of that mode, < 0 for the heuristic)
+hipError_t launch_col(const SweepArgs& a, int mode, int cfg, hipStream_t st);
 // the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c);
 // variant (tail_b only): 0 one workgroup per chain, 1 row blocks in
 // parallel with deeper K chunks, < 0 the heuristic (1 on levels of few boxes)
 size_t tail_workspace(int dld, int k);
+// the most box rows the split-precision products contract over
+int tail_mixed_max_rows();
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);

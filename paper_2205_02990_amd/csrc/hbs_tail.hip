@@ -211,6 +211,8 @@ size_t tail_workspace(int dld, int k) {
   return 6 * (size_t)dld * k + 2 * (size_t)((dld + 63) / 64) * k * k;
 }
 
+int tail_mixed_max_rows() { return kSliceChunks * kSliceK; }
+
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows

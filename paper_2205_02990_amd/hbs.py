@@ -18,6 +18,11 @@ LIB_PATH = os.path.join(_HERE, "libhbs.so")
 
 HBS_OK, HBS_EINVAL, HBS_ENOMEM, HBS_EDEVICE, HBS_ENUMERIC, HBS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp64": 0, "split": 1, "fp32_split": 1, "bf16": 2}
+TRUNCATION = {"qr": 0, "svd": 0x100}  # hbs_truncation, OR-ed into the precision argument
+
+
+def _mode(precision: str, truncation: str) -> int:
+    return PRECISION[precision] | TRUNCATION[truncation]
 PLAN_COLS = 20  # HBS_PLAN_COLS
 
 _lib = None
@@ -162,9 +167,9 @@ class Factors:
         self.k = int(k)
 
     @classmethod
-    def create(cls, tree: Tree, k: int, s: int, precision: str = "fp64"):
+    def create(cls, tree: Tree, k: int, s: int, precision: str = "fp64", truncation: str = "qr"):
         h = ctypes.c_void_p()
-        _check(load().hbs_factors_create(tree._h, int(k), int(s), PRECISION[precision], ctypes.byref(h)),
+        _check(load().hbs_factors_create(tree._h, int(k), int(s), _mode(precision, truncation), ctypes.byref(h)),
                "hbs_factors_create")
         f = cls(h, tree, k)
         f.s = int(s)
@@ -271,7 +276,7 @@ def _ptrs(ts, name):
 class Batch:
     """Independent compressions sharing one sweep (hbs_batch_*)."""
 
-    def __init__(self, trees, ks, ss, precision: str = "fp64"):
+    def __init__(self, trees, ks, ss, precision: str = "fp64", truncation: str = "qr"):
         lib = load()
         c = len(trees)
         self.trees = list(trees)
@@ -280,7 +285,7 @@ class Batch:
         th = (ctypes.c_void_p * c)(*[t._h.value for t in self.trees])
         h = ctypes.c_void_p()
         _check(lib.hbs_batch_create(c, th, (ctypes.c_int32 * c)(*self.ks), (ctypes.c_int32 * c)(*self.ss),
-                                    PRECISION[precision], ctypes.byref(h)), "hbs_batch_create")
+                                    _mode(precision, truncation), ctypes.byref(h)), "hbs_batch_create")
         self._h = h
 
     def __len__(self):
@@ -315,7 +320,7 @@ class Batch:
             self._h = None
 
 
-def compress_batched(trees, ks, Om, Y, Ps, Z, precision: str = "fp64", stream=None):
+def compress_batched(trees, ks, Om, Y, Ps, Z, precision: str = "fp64", stream=None, truncation: str = "qr"):
     """hbs_compress_batched: one Factors per instance."""
     c = len(trees)
     ld = [t.stride(0) for t in Om]
@@ -325,7 +330,8 @@ def compress_batched(trees, ks, Om, Y, Ps, Z, precision: str = "fp64", stream=No
     _check(load().hbs_compress_batched(c, th, (ctypes.c_int32 * c)(*[int(k) for k in ks]),
                                        (ctypes.c_int32 * c)(*ss), _ptrs(Om, "Omega"), _ptrs(Y, "Y"),
                                        _ptrs(Ps, "Psi"), _ptrs(Z, "Z"), (ctypes.c_int64 * c)(*ld),
-                                       PRECISION[precision], _stream(stream), out), "hbs_compress_batched")
+                                       _mode(precision, truncation), _stream(stream), out),
+           "hbs_compress_batched")
     res = []
     for i in range(c):
         f = Factors(ctypes.c_void_p(out[i]), trees[i], ks[i])
@@ -334,9 +340,10 @@ def compress_batched(trees, ks, Om, Y, Ps, Z, precision: str = "fp64", stream=No
     return res
 
 
-def compress(tree: Tree, k: int, Om, Y, Ps, Z, precision: str = "fp64", stream=None) -> Factors:
+def compress(tree: Tree, k: int, Om, Y, Ps, Z, precision: str = "fp64", stream=None,
+             truncation: str = "qr") -> Factors:
     """Algorithm 2 on the GPU: allocate a factor set and fill it."""
-    f = Factors.create(tree, k, Om.shape[1], precision)
+    f = Factors.create(tree, k, Om.shape[1], precision, truncation)
     return f.compress_into(Om, Y, Ps, Z, stream)
 
 

@@ -66,23 +66,48 @@ def test_tree_rejects_bad_arguments():
         assert e.value.status == hbs.HBS_EINVAL
 
 
+@pytest.mark.parametrize("precision", ["fp64", "split"])
+@pytest.mark.parametrize("truncation", ["qr", "svd"])
 @pytest.mark.parametrize("n,leaf,k,s,status", [
     (1024, 32, 16, 47, "EINVAL"),   # s - m < k at the leaves
-    (1024, 32, 16, 47, "EINVAL"),
     (1024, 32, 16, 32 + 16 - 1, "EINVAL"),
     (1024, 32, 33, 200, "EINVAL"),  # leaves smaller than k
-    (1024, 32, 16, 47, "EINVAL"),
     (1024, 32, 0, 58, "EINVAL"),
+    (1024, 32, 16, 0, "EINVAL"),
     (1024, 32, 16, 3 * 16 - 1, "EINVAL"),  # inner boxes of 2k rows need s >= 3k
+    (1024, 64, 16, 63, "EINVAL"),   # s < 2k + ... : leaves of 64 rows leave no k-column sketch
     (40, 64, 4, 39, "EINVAL"),      # root-only: s must be >= N
     (1024, 512, 16, 600, "EUNSUPPORTED"),  # leaves of 512 rows: no compiled tile class
 ])
-def test_factor_creation_validates_before_device_work(n, leaf, k, s, status):
+def test_factor_creation_validates_before_device_work(n, leaf, k, s, status, truncation, precision):
     hbs = _lib()
     t = hbs.Tree(n, leaf)
     with pytest.raises(hbs.HBSError) as e:
-        hbs.Factors.create(t, k, s)
+        hbs.Factors.create(t, k, s, precision, truncation)
     assert e.value.status == getattr(hbs, "HBS_" + status)
+
+
+@pytest.mark.parametrize("truncation", ["qr", "svd"])
+def test_split_precision_rejects_boxes_over_128_rows(truncation):
+    """The split-precision products contract over at most 128 box rows (as
+    many as the largest QR tile holds): a factor set with larger boxes
+    (leaves of 200 rows, or k = 80 so that the inner boxes have 160) is
+    refused at creation, before any launch, never at compression time."""
+    hbs = _lib()
+    for n, leaf, k, s in [(1600, 200, 60, 400), (2560, 160, 80, 250)]:
+        t = hbs.Tree(n, leaf)
+        with pytest.raises(hbs.HBSError) as e:
+            hbs.Factors.create(t, k, s, "split", truncation)
+        assert e.value.status == hbs.HBS_EUNSUPPORTED, (n, leaf, k, s)
+
+
+def test_unknown_mode_bits_are_rejected():
+    hbs = _lib()
+    lib = hbs.load()
+    t = hbs.Tree(1024, 32)
+    h = ctypes.c_void_p()
+    assert lib.hbs_factors_create(t._h, 16, 58, 0x1000, ctypes.byref(h)) == hbs.HBS_EINVAL
+    assert lib.hbs_factors_create(t._h, 16, 58, 0x100 | 7, ctypes.byref(h)) == hbs.HBS_EUNSUPPORTED
 
 
 def test_reporting_entry_points_validate_before_device_work():

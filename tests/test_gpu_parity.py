@@ -312,3 +312,46 @@ def test_autotuned_and_heuristic_tiles_agree(hbs, n, k, leaf, s, monkeypatch):
               f"{[(p['lq']['threads'], p['lq']['chunks'], p['tail_b']) for p in plan]}", flush=True)
         assert e <= 1e-12
     assert rel(out["1"], out["0"]) <= 1e-12
+
+
+def test_back_to_back_calls_without_host_sync(hbs):
+    """Two compressions of different inputs into one factor set, each followed
+    by an apply, enqueued with no host synchronisation between them while the
+    stream is still busy with earlier work: every result matches its own
+    oracle (the inputs are captured per call, never rewritten under a queued
+    upload).  Then a compression on one stream and an apply on another: the
+    library orders them."""
+    n, k, leaf, s = 3001, 16, 32, 58
+    ca = synthetic_case(n, k, leaf, s, extra=(1,))
+    cb = synthetic_case(n, k, leaf, s, extra=(2,))
+    oa = ohbs.compress(ca["levels"], k, ca["Om"], ca["Y"], ca["Ps"], ca["Z"])
+    ob = ohbs.compress(cb["levels"], k, cb["Om"], cb["Y"], cb["Ps"], cb["Z"])
+    G = ca["G"]
+    tree = hbs.Tree(n, leaf)
+    f = hbs.Factors.create(tree, k, s)
+    ia = [dev(ca[x]) for x in ("Om", "Y", "Ps", "Z")]
+    ib = [dev(cb[x]) for x in ("Om", "Y", "Ps", "Z")]
+    Gd = dev(G)
+    f.compress_into(*ia)  # first call: tiles tuned, graph captured
+    torch.cuda.synchronize()
+    big = torch.randn(4096, 4096, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        busy = big @ big  # keeps the stream busy while the host runs ahead
+        f.compress_into(*ia)
+        out_a = f.apply(Gd)
+        f.compress_into(*ib)
+        out_b = f.apply(Gd)
+        del busy
+        torch.cuda.synchronize()
+        ea = rel(host(out_a), ohbs.apply(oa, G))
+        eb = rel(host(out_b), ohbs.apply(ob, G))
+        assert ea <= 1e-12 and eb <= 1e-12, (rep, ea, eb)
+    # compress on a side stream, apply on the current one, no sync between
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        busy = big @ big
+        f.compress_into(*ia)
+    out = f.apply(Gd)
+    torch.cuda.synchronize()
+    assert rel(host(out), ohbs.apply(oa, G)) <= 1e-12
+    f.check()
