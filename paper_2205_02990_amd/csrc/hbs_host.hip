@@ -90,6 +90,7 @@ struct BatchImpl {
   hbs_precision prec = HBS_FP64;
   bool svd = false;       // bases by SVD truncation of the sketches (else truncated pivoted QR)
   int jac_sweeps = 3;     // SVD truncation: most Jacobi sweeps per sketch
+  int slices = 8;         // split precision: 7-bit slices per operand
   std::vector<void*> allocs;
   // The panel-source table: the host template (callers' inputs are written
   // into it), and a ring of pinned copies, one per call, each reused only
@@ -405,6 +406,7 @@ hbs_status build_sweep(BatchImpl* b) {
       ln.args.mixed = b->prec == HBS_FP32_SPLIT ? 1 : 0;
       ln.args.svd = b->svd ? 1 : 0;
       ln.args.jac_sweeps = b->jac_sweeps;
+      ln.args.slices = b->slices;
       ln.args.flag = b->flag;
       b->launches.push_back(ln);
     }
@@ -442,10 +444,10 @@ hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
 // device and launch shape for the life of the process, so later batches of
 // the same shapes reuse them without timing.
 struct TuneKey {
-  int dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps;
+  int dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps, slices;
   bool operator<(const TuneKey& o) const {
-    return std::tie(dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps) <
-           std::tie(o.dev, o.kind, o.mmax, o.mmin, o.s, o.k, o.nboxes, o.mixed, o.root, o.svd, o.sweeps);
+    return std::tie(dev, kind, mmax, mmin, s, k, nboxes, mixed, root, svd, sweeps, slices) <
+           std::tie(o.dev, o.kind, o.mmax, o.mmin, o.s, o.k, o.nboxes, o.mixed, o.root, o.svd, o.sweeps, o.slices);
   }
 };
 std::mutex g_tune_mu;
@@ -453,7 +455,8 @@ std::map<TuneKey, std::pair<int, int>> g_tune;  // kind 0: (lq cfg, ns); 1: (col
                                                 // 3: (Jacobi-pass col cfg, 0)
 
 TuneKey tune_key(int dev, int kind, const hbs::SweepArgs& a) {
-  return TuneKey{dev, kind, a.mmax, a.mmin, a.s, a.k, a.nboxes, a.mixed, a.root, a.svd, a.svd ? a.jac_sweeps : 0};
+  return TuneKey{dev, kind, a.mmax, a.mmin, a.s, a.k, a.nboxes, a.mixed, a.root, a.svd, a.svd ? a.jac_sweeps : 0,
+                 a.mixed ? a.slices : 0};
 }
 
 bool tune_lookup(const TuneKey& key, std::pair<int, int>* v) {
@@ -646,6 +649,8 @@ hbs_status make_batch(int32_t count, const hbs_tree* const* trees, const int32_t
     b->autotune = !(ev && ev[0] == '0');
     const char* js = std::getenv("HBS_JACOBI_SWEEPS");  // most Jacobi sweeps of the SVD truncation
     if (js) b->jac_sweeps = std::max(1, std::min(20, std::atoi(js)));
+    const char* sl = std::getenv("HBS_SPLIT_SLICES");  // 7-bit slices per operand of the split path
+    if (sl) b->slices = std::max(6, std::min(8, std::atoi(sl)));
   }
   HIP_TRY(b->alloc((void**)&b->flag, sizeof(int32_t)));
   HIP_TRY(hipMemset(b->flag, 0, sizeof(int32_t)));

@@ -42,6 +42,7 @@ struct SweepArgs {
   int32_t nboxes, k, s, mmax, mmin;
   int32_t root;   // 1: only W = Y Omega^dagger of each box (written to D)
   int32_t mixed;  // 1: split-precision bulk products in the tail kernels
+  int32_t slices; // split precision: 7-bit slices per operand (6..8)
   int32_t svd;    // 1: bases by SVD truncation of the sketch, 0: truncated pivoted QR
   int32_t jac_sweeps;  // SVD truncation: most Jacobi sweeps per sketch
   int32_t* flag;

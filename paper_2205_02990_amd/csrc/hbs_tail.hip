@@ -25,20 +25,18 @@
 namespace hbs {
 namespace {
 
-constexpr int kSlices = 8;  // 56 bits of every operand: FP64-level error per product
-
-template <bool MIXED>
-struct TailSmem;
-template <>
-struct TailSmem<false> {
-  MfmaSmem<16> g;
-};
-template <>
-struct TailSmem<true> {
+// Split-precision products cut every operand into S exact 7-bit slices (7 S
+// bits: 8 gives FP64-level error per product); S = 0 is the FP64 path.
+template <int S>
+struct TailSmem {
   union {
     MfmaSmem<16> g;
-    SliceSmem<kSlices> sl;
+    SliceSmem<S> sl;
   };
+};
+template <>
+struct TailSmem<0> {
+  MfmaSmem<16> g;
 };
 
 // Workspace of one box: F | Q | E | H (dld x k each) | T0 | T (k x dld each) |
@@ -87,32 +85,32 @@ inline dim3 xcd_grid(int nboxes, int ny) {
 }
 
 // C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
-template <bool MIXED, int KCH>
-__device__ __forceinline__ void bulk(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
+template <int S, int KCH>
+__device__ __forceinline__ void bulk(TailSmem<S>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
                             const double* R, int64_t ldr, double beta, const double* C0, int64_t ldc0, double* C,
                             int64_t ldc) {
-  if constexpr (MIXED)
-    sliced_lt<kSlices, KCH>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
+  if constexpr (S > 0)
+    sliced_lt<S, KCH>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
   else
     mfma_gemm<16>(M, N, K, alpha, L, 1, ldl, R, ldr, 1, beta, C0, ldc0, C, ldc, sm.g);
 }
 
 // FP64 product by the workgroup of either tail variant
-template <bool MIXED>
-__device__ __forceinline__ void dgemm(TailSmem<MIXED>& sm, int M, int N, int K, double alpha, const double* A, int64_t sar,
+template <int S>
+__device__ __forceinline__ void dgemm(TailSmem<S>& sm, int M, int N, int K, double alpha, const double* A, int64_t sar,
                              int64_t sac, const double* B, int64_t sbr, int64_t sbc, double beta, const double* C0,
                              int64_t ldc0, double* C, int64_t ldc) {
-  mfma_gemm<16, MIXED ? kSliceThreads : kGemmThreads>(M, N, K, alpha, A, sar, sac, B, sbr, sbc, beta, C0, ldc0, C,
+  mfma_gemm<16, (S > 0 ? kSliceThreads : kGemmThreads)>(M, N, K, alpha, A, sar, sac, B, sbr, sbc, beta, C0, ldc0, C,
                                                       ldc, sm.g);
 }
 
-template <bool MIXED>
-constexpr int tail_threads() { return MIXED ? kSliceThreads : kGemmThreads; }
+template <int S>
+constexpr int tail_threads() { return S > 0 ? kSliceThreads : kGemmThreads; }
 
 // grid (boxes, 3 mt + 4 st): mt = row tiles of the box, st = 64-column tiles of s
-template <bool MIXED, int KCH = kSliceChunks>
-__global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs a) {
-  __shared__ TailSmem<MIXED> sm;
+template <int S, int KCH = kSliceChunks>
+__global__ void __launch_bounds__(tail_threads<S>()) tail_a_kernel(SweepArgs a) {
+  __shared__ TailSmem<S> sm;
   const int mt = (a.mmax + 63) / 64;
   const XcdTile tl = xcd_tile(3 * mt + 4 * ((a.s + 63) / 64));
   if (tl.box >= a.nboxes) return;
@@ -129,7 +127,7 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs
     const bool useV = (which == kOm) || (which == kZ);
     const double* L = useV ? bx.V : bx.U;
     const double* P = ps.p[which] + bx.row0 * ld + c0;
-    bulk<MIXED, KCH>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
+    bulk<S, KCH>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
     return;
   }
   const int which = y / mt, r0 = (y % mt) * 64;
@@ -137,13 +135,13 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_a_kernel(SweepArgs
   const int nr = min(64, m - r0);
   TailWs ws(bx.T, dld, k);
   if (which == 0)  // F = X U (rows r0..)
-    dgemm<MIXED>(sm, nr, k, m, 1.0, bx.X + (int64_t)r0 * dld, dld, 1, bx.U, k, 1, 0.0, nullptr, 0,
+    dgemm<S>(sm, nr, k, m, 1.0, bx.X + (int64_t)r0 * dld, dld, 1, bx.U, k, 1, 0.0, nullptr, 0,
                  ws.F + (int64_t)r0 * k, k);
   else if (which == 1)  // Q = W V
-    dgemm<MIXED>(sm, nr, k, m, 1.0, bx.W + (int64_t)r0 * dld, dld, 1, bx.V, k, 1, 0.0, nullptr, 0,
+    dgemm<S>(sm, nr, k, m, 1.0, bx.W + (int64_t)r0 * dld, dld, 1, bx.V, k, 1, 0.0, nullptr, 0,
                  ws.Q + (int64_t)r0 * k, k);
   else  // T0 = U^* W (columns r0..)
-    dgemm<MIXED>(sm, k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld);
+    dgemm<S>(sm, k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld);
 }
 
 // grid (boxes, 2 nrb): chain 0 forms G = V^* F, then rows of E = F - V G and
@@ -176,9 +174,9 @@ __global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
 }
 
 // grid (boxes, mt^2 + 2 st)
-template <bool MIXED, int KCH = kSliceChunks>
-__global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs a) {
-  __shared__ TailSmem<MIXED> sm;
+template <int S, int KCH = kSliceChunks>
+__global__ void __launch_bounds__(tail_threads<S>()) tail_c_kernel(SweepArgs a) {
+  __shared__ TailSmem<S> sm;
   const int mt = (a.mmax + 63) / 64;
   const XcdTile tl = xcd_tile(mt * mt + 2 * ((a.s + 63) / 64));
   if (tl.box >= a.nboxes) return;
@@ -189,7 +187,7 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs
   if (y < mt * mt) {  // D = W - U T, one 64 x 64 tile
     const int r0 = (y / mt) * 64, c0 = (y % mt) * 64;
     if (r0 >= m || c0 >= m) return;
-    dgemm<MIXED>(sm, min(64, m - r0), min(64, m - c0), k, -1.0, bx.U + (int64_t)r0 * k, k, 1, ws.T + c0, dld, 1,
+    dgemm<S>(sm, min(64, m - r0), min(64, m - c0), k, -1.0, bx.U + (int64_t)r0 * k, k, 1, ws.T + c0, dld, 1,
                  1.0, bx.W + (int64_t)r0 * dld + c0, dld, bx.D + (int64_t)r0 * dld + c0, dld);
     return;
   }
@@ -202,7 +200,7 @@ __global__ void __launch_bounds__(tail_threads<MIXED>()) tail_c_kernel(SweepArgs
   const double* L = which ? ws.H : ws.E;
   const double* P = ps.p[2 * which] + bx.row0 * ld + c0;  // Omega or Psi
   double* out = bx.np[2 * which + 1] + c0;                 // Y' or Z'
-  bulk<MIXED, KCH>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
+  bulk<S, KCH>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
 }
 
 }  // namespace
@@ -213,18 +211,47 @@ size_t tail_workspace(int dld, int k) {
 
 int tail_mixed_max_rows() { return kSliceChunks * kSliceK; }
 
+namespace {
+
+// the split-precision launch of tail_a or tail_c for S slices, with one
+// staging chunk when the boxes have at most kSliceK rows
+struct TailA {
+  template <int S, int KCH>
+  static void launch(dim3 grid, hipStream_t st, const SweepArgs& a) {
+    hipLaunchKernelGGL((tail_a_kernel<S, KCH>), grid, dim3(kSliceThreads), 0, st, a);
+  }
+};
+struct TailC {
+  template <int S, int KCH>
+  static void launch(dim3 grid, hipStream_t st, const SweepArgs& a) {
+    hipLaunchKernelGGL((tail_c_kernel<S, KCH>), grid, dim3(kSliceThreads), 0, st, a);
+  }
+};
+template <class K>
+void launch_sliced(int slices, bool one_chunk, dim3 grid, hipStream_t st, const SweepArgs& a) {
+  switch (slices * 2 + (one_chunk ? 1 : 0)) {
+    case 12: K::template launch<6, kSliceChunks>(grid, st, a); break;
+    case 13: K::template launch<6, 1>(grid, st, a); break;
+    case 14: K::template launch<7, kSliceChunks>(grid, st, a); break;
+    case 15: K::template launch<7, 1>(grid, st, a); break;
+    case 16: K::template launch<8, kSliceChunks>(grid, st, a); break;
+    default: K::template launch<8, 1>(grid, st, a); break;
+  }
+}
+
+}  // namespace
+
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
   if (xcd_total(a.nboxes, 3 * mt + 4 * sct) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (a.mixed && (a.slices < 6 || a.slices > 8)) return hipErrorInvalidValue;
   if (part == 0) {
     const dim3 grid = xcd_grid(a.nboxes, 3 * mt + 4 * sct);
-    if (a.mixed && a.mmax <= kSliceK)
-      hipLaunchKernelGGL((tail_a_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
-    else if (a.mixed)
-      hipLaunchKernelGGL(tail_a_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
+    if (!a.mixed)
+      hipLaunchKernelGGL(tail_a_kernel<0>, grid, dim3(kGemmThreads), 0, st, a);
     else
-      hipLaunchKernelGGL(tail_a_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
+      launch_sliced<TailA>(a.slices, a.mmax <= kSliceK, grid, st, a);
   } else if (part == 1) {
     // few boxes: latency bound, row blocks in parallel and deeper K chunks
     if (variant < 0) variant = a.nboxes < 256 ? 1 : 0;
@@ -234,12 +261,10 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
       hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
   } else {
     const dim3 grid = xcd_grid(a.nboxes, mt * mt + 2 * sct);
-    if (a.mixed && a.mmax <= kSliceK)
-      hipLaunchKernelGGL((tail_c_kernel<true, 1>), grid, dim3(kSliceThreads), 0, st, a);
-    else if (a.mixed)
-      hipLaunchKernelGGL(tail_c_kernel<true>, grid, dim3(kSliceThreads), 0, st, a);
+    if (!a.mixed)
+      hipLaunchKernelGGL(tail_c_kernel<0>, grid, dim3(kGemmThreads), 0, st, a);
     else
-      hipLaunchKernelGGL(tail_c_kernel<false>, grid, dim3(kGemmThreads), 0, st, a);
+      launch_sliced<TailC>(a.slices, a.mmax <= kSliceK, grid, st, a);
   }
   return hipGetLastError();
 }

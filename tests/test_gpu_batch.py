@@ -130,32 +130,36 @@ def test_batch512_full_size(hbs, progress):
     ks, ss = [x["k"] for x in spec], [x["s"] for x in spec]
     worst = {}
     batches = {}
-    for precision in ("fp64", "split"):
-        b = hbs.Batch(trees, ks, ss, precision)
+    modes = [("fp64", "qr"), ("split", "qr"), ("fp64", "svd"), ("split", "svd")]
+    for precision, trunc in modes:
+        b = hbs.Batch(trees, ks, ss, precision, trunc)
         b.compress(Om, Y, Ps, Z)  # the first sweep also autotunes the tiles
         b.factors(0).check()
-        progress(f"[batch512] {precision}: compressed; checking every instance")
+        progress(f"[batch512] {precision}/{trunc}: compressed; checking every instance")
         w = 0.0
         for i, x in enumerate(spec):
             AG = ohbs.apply(gens[i][1], G[i])
             e = rel(host(b.factors(i).apply(dev(G[i]))), AG)
             w = max(w, e)
-        worst[precision] = w
-        batches[precision] = b
-        progress(f"[batch512] {precision}: worst relative apply error vs generator {w:.3e}")
-    # depth <= 10 here; the method's own rounding growth up the tree keeps
-    # the oracle below 3e-11 at depth 11 with these parameters
-    assert worst["fp64"] <= 1e-10
-    assert worst["split"] <= 1e-10
+        worst[precision, trunc] = w
+        batches[precision, trunc] = b
+        progress(f"[batch512] {precision}/{trunc}: worst relative apply error vs generator {w:.3e}")
+    # depth <= 10 here.  The truncated-QR reading passes rounding up the tree
+    # (about 2.5x per level: 5e-12 at depth 9, 2.5e-11 at 11 with k = 32), the
+    # SVD reading does not.
+    assert worst["fp64", "qr"] <= 2e-11 and worst["split", "qr"] <= 2e-11
+    assert worst["fp64", "svd"] <= 2e-12
+    assert worst["split", "svd"] <= 1e-10
     order = sorted(range(len(spec)), key=lambda i: spec[i]["n"])
     rng = inputs.streams(wl["id"], 1, extra=(0x5A3,))[0]
     pick = sorted({order[0], order[-1], *rng.choice(len(spec), 2, replace=False).tolist()})
     for i in pick:
         levels, gen, om, ps = gens[i]
         x = spec[i]
-        orc = ohbs.compress(levels, x["k"], om, host(Y[i]), ps, host(Z[i]))
-        OG = ohbs.apply(orc, G[i])
-        e = {p: rel(host(batches[p].factors(i).apply(dev(G[i]))), OG) for p in batches}
-        progress(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)}: vs oracle "
-                 f"fp64 {e['fp64']:.3e}, split {e['split']:.3e}")
-        assert e["fp64"] <= 1e-10 and e["split"] <= 1e-10
+        for trunc in ("qr", "svd"):
+            orc = ohbs.compress(levels, x["k"], om, host(Y[i]), ps, host(Z[i]), truncation=trunc)
+            OG = ohbs.apply(orc, G[i])
+            e = {p: rel(host(batches[p, trunc].factors(i).apply(dev(G[i]))), OG) for p in ("fp64", "split")}
+            progress(f"[batch512] instance {i} n={x['n']} k={x['k']} depth {otree.depth(levels)} {trunc}: vs oracle "
+                     f"fp64 {e['fp64']:.3e}, split {e['split']:.3e}")
+            assert e["fp64"] <= (2e-11 if trunc == "qr" else 1e-12) and e["split"] <= 1e-10
