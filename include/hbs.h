@@ -183,6 +183,23 @@ hbs_status hbs_compress_batched(int32_t count, const hbs_tree* const* trees, con
 hbs_status hbs_apply(hbs_factors* f, int transpose, const double* X, double* Out, int64_t nvec,
                      int64_t ldx, void* hip_stream);
 
+/* hbs_apply for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same operation and kernels, but the level blocks of Algorithm 1 live in a
+ * library-owned static device array of 64 MiB per GPU (held from module load
+ * until the process ends) instead of memory allocated on first use; this
+ * call never allocates.  nvec may be at most hbs_apply_static_max(f) (the
+ * blocks of one vector take sum over levels l = 1..L of 2^l k doubles, twice);
+ * larger requests return HBS_EUNSUPPORTED before anything is enqueued.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on the device
+ * race (calls on one factor set are ordered by the library, calls on
+ * different factor sets on different streams are not). */
+hbs_status hbs_apply_static(hbs_factors* f, int transpose, const double* X, double* Out, int64_t nvec,
+                            int64_t ldx, void* hip_stream);
+/* The largest nvec hbs_apply_static accepts for f (INT64_MAX when L = 0:
+ * no level blocks); -1 for NULL. */
+int64_t    hbs_apply_static_max(const hbs_factors* f);
+
 /* Wrap known factors as a factor set, e.g. the generators of a synthetic HBS
  * matrix, so that hbs_apply acts as its black box.  `levels` is a HOST array
  * of L views (levels[l-1] describes level l, layout as hbs_level_view, device

@@ -684,6 +684,39 @@ namespace hbs {
 int64_t factors_n(const hbs_factors* f) { return inst_of(f).tree.n; }
 }  // namespace hbs
 
+// Device scratch of hbs_apply_static: the level blocks q-hat and u-hat of
+// Algorithm 1 (two halves of kApplyScratch doubles / 2).  Every GPU the
+// library runs on holds its own copy from module load until the process ends.
+// Host code never passes this name to a kernel: it is a host-side stand-in;
+// the device address comes from hipGetSymbolAddress (apply_scratch_ptr).
+constexpr size_t kApplyScratch = (size_t)8 << 20;  // 64 MiB of doubles per device
+static __device__ __align__(256) double scratch[kApplyScratch];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+hipError_t apply_scratch_ptr(double** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char* hbs_status_str(hbs_status s) {
@@ -882,6 +915,30 @@ hbs_status hbs_apply(hbs_factors* f, int transpose, const double* Xin, double* O
   if (res != HBS_OK) return res;
   HIP_TRY(batch_leave(b, st));
   return HBS_OK;
+}
+
+hbs_status hbs_apply_static(hbs_factors* f, int transpose, const double* Xin, double* Out, int64_t nvec,
+                            int64_t ldx, void* hip_stream) {
+  if (!f || !Xin || !Out || nvec < 1 || ldx < nvec) return HBS_EINVAL;
+  hipStream_t st = (hipStream_t)hip_stream;
+  BatchImpl* b = f->b.get();
+  Instance& in = inst_of(f);
+  const size_t half = kApplyScratch / 2;
+  if ((size_t)in.hoff[in.L + 1] * (size_t)nvec > half) return HBS_EUNSUPPORTED;
+  double* sp = nullptr;
+  HIP_TRY(apply_scratch_ptr(&sp));
+  HIP_TRY(batch_enter(b, st));
+  hbs_status res = apply_body(f, transpose, Xin, Out, nvec, ldx, sp, sp + half, st);
+  if (res != HBS_OK) return res;
+  HIP_TRY(batch_leave(b, st));
+  return HBS_OK;
+}
+
+int64_t hbs_apply_static_max(const hbs_factors* f) {
+  if (!f) return -1;
+  const Instance& in = inst_of(f);
+  const int64_t rows = in.hoff[in.L + 1];
+  return rows > 0 ? (int64_t)(kApplyScratch / 2) / rows : INT64_MAX;
 }
 
 }  // extern "C"

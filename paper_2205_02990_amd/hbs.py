@@ -61,6 +61,8 @@ def load():
         "hbs_compress_into": (I32, [P, VP, VP, VP, VP, I64, VP]),
         "hbs_compress": (I32, [P, I32, I32, VP, VP, VP, VP, I64, I32, VP, ctypes.POINTER(P)]),
         "hbs_apply": (I32, [P, ctypes.c_int, VP, VP, I64, I64, VP]),
+        "hbs_apply_static": (I32, [P, ctypes.c_int, VP, VP, I64, I64, VP]),
+        "hbs_apply_static_max": (I64, [P]),
         "hbs_factors_import": (I32, [P, I32, ctypes.POINTER(LevelView), VP, VP, ctypes.POINTER(P)]),
         "hbs_level": (I32, [P, I32, ctypes.POINTER(LevelView)]),
         "hbs_root": (I32, [P, ctypes.POINTER(P), ctypes.POINTER(I32)]),
