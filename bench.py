@@ -155,14 +155,18 @@ def _oracle_synthetic(inputs, n, k, leaf, s, rs):
     return levels, k, Om, ohbs.apply(gen, Om), Ps, ohbs.apply(gen, Ps, transpose=True)
 
 
-def cpu_result(jobs, single_jobs, sample):
-    rows, dt, thr = _timed_oracle(jobs)
-    out = {"value": rows / dt, "unit": "rows/s", "cores": thr, "kind": "oracle",
-           "sample": f"{sample}; {rows} rows in {dt:.1f} s; host os.cpu_count()={os.cpu_count()}"}
-    if single_jobs:
-        r1, d1, _ = _timed_oracle(single_jobs, single_thread=True)
-        out["single_thread"] = {"value": r1 / d1, "unit": "rows/s", "cores": 1,
-                                "sample": f"{r1} rows in {d1:.1f} s (BLAS held to one thread)"}
+def cpu_result(jobs, multi_jobs, sample):
+    """The oracle's rate on `jobs` with BLAS held to one thread (faster on
+    these small boxes: threads cost more than the products they split) and,
+    for comparison, on `multi_jobs` with the host's default BLAS threads."""
+    rows, dt, _ = _timed_oracle(jobs, single_thread=True)
+    out = {"value": rows / dt, "unit": "rows/s", "cores": 1, "kind": "oracle",
+           "sample": f"{sample}; {rows} rows in {dt:.1f} s with BLAS held to one thread; "
+                     f"host os.cpu_count()={os.cpu_count()}"}
+    if multi_jobs:
+        r1, d1, thr = _timed_oracle(multi_jobs)
+        out["default_threads"] = {"value": r1 / d1, "unit": "rows/s", "cores": thr,
+                                  "sample": f"{r1} rows in {d1:.1f} s with the default BLAS threads"}
     return out
 
 
@@ -224,9 +228,9 @@ def setup_logkernel(wl, args, hbs, torch, inputs, dev):
         sub = otree.cluster_tree(b - a, leaf)
         YZ = olog.sample(x, y, np.hstack((Om, Ps)), np.arange(a, b))  # the oracle's samples of those rows
         job = (sub, k, Om[a:b], YZ[:, :s], Ps[a:b], YZ[:, s:])
-        return cpu_result([job], [], f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of "
-                                     f"level {args.cpu_subtree_level} of {args.workload} (all its "
-                                     f"{otree.depth(sub)} levels)")
+        return cpu_result([job], [job], f"oracle Algorithm 2 on the {b - a}-row subtree under the first node of "
+                                        f"level {args.cpu_subtree_level} of {args.workload} (all its "
+                                        f"{otree.depth(sub)} levels)")
     P.cpu = cpu
     return P
 
@@ -287,10 +291,10 @@ def setup_synthetic(wl, args, hbs, torch, inputs, dev):
         # a smaller instance of the same shape, drawn and sampled by the oracle
         nc = min(n, leaf * 2 ** 10)
         job = _oracle_synthetic(inputs, nc, k, leaf, s, inputs.streams(wl["id"], extra=(0xC0,)))
-        single = [job] if nc <= leaf * 2 ** 8 else \
-            [_oracle_synthetic(inputs, leaf * 2 ** 8, k, leaf, s, inputs.streams(wl["id"], extra=(0xC1,)))]
-        return cpu_result([job], single, f"oracle Algorithm 2 on an exact-rank instance of {nc} rows with the "
-                                         f"workload's k = {k}, leaf {leaf}, s = {s}, drawn and sampled on the CPU")
+        multi = [job] if nc <= leaf * 2 ** 7 else \
+            [_oracle_synthetic(inputs, leaf * 2 ** 7, k, leaf, s, inputs.streams(wl["id"], extra=(0xC1,)))]
+        return cpu_result([job], multi, f"oracle Algorithm 2 on an exact-rank instance of {nc} rows with the "
+                                        f"workload's k = {k}, leaf {leaf}, s = {s}, drawn and sampled on the CPU")
     P.cpu = cpu
     return P
 
@@ -336,8 +340,8 @@ def setup_batch(wl, args, hbs, torch, inputs, dev):
         # drawn and sampled by the oracle with each instance's own seeds
         jobs = [_oracle_synthetic(inputs, x["n"], x["k"], x["leaf_max"], x["s"],
                                   inputs.streams(wl["id"], extra=(x["index"],))) for x in spec[:32]]
-        return cpu_result(jobs, jobs[:8], "oracle Algorithm 2 on the first 32 of the 512 instances, each drawn and "
-                                          "sampled on the CPU from its own seeds (single thread: the first 8)")
+        return cpu_result(jobs, jobs[:4], "oracle Algorithm 2 on the first 32 of the 512 instances, each drawn and "
+                                          "sampled on the CPU from its own seeds (default threads: the first 4)")
     P.cpu = cpu
     return P
 
@@ -404,6 +408,8 @@ def main():
     ap.add_argument("--path", default="both", choices=["both", "fp64", "split"],
                     help="both: the split-precision path gives `value`, the FP64 path runs beside it")
     ap.add_argument("--truncation", default="qr", choices=["qr", "svd"])
+    ap.add_argument("--n", type=int, default=0,
+                    help="single-instance workloads: N other than the workload's own (same k, leaf, s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-subtree-level", type=int, default=4)
     ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
@@ -428,6 +434,10 @@ def main():
     from paper_2205_02990_amd import hbs
 
     wl = dict(inputs.WORKLOADS[args.workload])
+    if args.n:
+        if wl["kind"] == "batch":
+            raise SystemExit("--n applies to single-instance workloads")
+        wl["n"] = args.n
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hbs.load()
@@ -481,7 +491,8 @@ def main():
         "metric": METRIC, "value": head["rows_per_s"], "unit": "rows/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+i8-slices" if paths[0] == "split" else "f64", "data": "synthetic",
-        "config": {"workload": args.workload, **P.config, "path": paths[0], "truncation": args.truncation},
+        "config": {"workload": args.workload + (f" at N = {args.n}" if args.n else ""), **P.config,
+                   "path": paths[0], "truncation": args.truncation},
         "roofline": roofline,
         "rel_apply_err": head["rel_apply_err"], "power_rel_err": head["power_rel_err"],
         "paths": {p: strip(res[p]) for p in paths},

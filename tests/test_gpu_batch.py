@@ -126,6 +126,7 @@ def test_batch512_full_size(hbs, progress):
         Y.append(dev(ohbs.apply(gen, om)))
         Z.append(dev(ohbs.apply(gen, ps, transpose=True)))
         trees.append(hbs.Tree(x["n"], x["leaf_max"]))
+    AGs = [ohbs.apply(gens[i][1], G[i]) for i in range(len(spec))]  # each generator on its probes
     progress("[batch512] inputs ready; compressing")
     ks, ss = [x["k"] for x in spec], [x["s"] for x in spec]
     worst = {}
@@ -138,8 +139,7 @@ def test_batch512_full_size(hbs, progress):
         progress(f"[batch512] {precision}/{trunc}: compressed; checking every instance")
         w = 0.0
         for i, x in enumerate(spec):
-            AG = ohbs.apply(gens[i][1], G[i])
-            e = rel(host(b.factors(i).apply(dev(G[i]))), AG)
+            e = rel(host(b.factors(i).apply(dev(G[i]))), AGs[i])
             w = max(w, e)
         worst[precision, trunc] = w
         batches[precision, trunc] = b

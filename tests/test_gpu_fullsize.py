@@ -205,3 +205,38 @@ def test_exact_rank_depth11_truncated_qr(hbs, progress):
     progress(f"[fullsize] depth 11: oracle {e_orc:.3e}, GPU {e_gpu:.3e} vs generator; GPU vs oracle {e_par:.3e}")
     assert e_orc <= 5e-11 and e_gpu <= 5e-11
     assert e_par <= 5e-11
+
+
+@pytest.mark.timeout(900)
+def test_logkernel_n65536_against_oracle_sweep(hbs, progress):
+    """The 65536-point log-kernel workload at full size against the oracle's
+    whole sweep on the oracle's own samples (formed on the CPU, 320 columns
+    of the dense kernel), FP64 and split paths, truncated-QR reading.  Both
+    sides truncate the same sketches with the same pivot rule, so they agree
+    far below the truncation error itself (1.5e-10)."""
+    import threadpoolctl
+    wl = inputs.WORKLOADS["logkernel_ellipse_n65536_k50"]
+    n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
+    x, y = inputs.ellipse_points(n, wl["a"], wl["b"])
+    rs = inputs.streams(wl["id"])
+    Om = inputs.gaussian(rs[inputs.STREAM_OMEGA], n, s)
+    Ps = inputs.gaussian(rs[inputs.STREAM_PSI], n, s)
+    progress(f"[fullsize] log kernel N={n}: the oracle's samples (dense rows, CPU)")
+    YZ = olog.sample(x, y, np.hstack((Om, Ps)), block=2048)
+    Y, Z = np.ascontiguousarray(YZ[:, :s]), np.ascontiguousarray(YZ[:, s:])
+    del YZ
+    progress("[fullsize] oracle sweep (one BLAS thread: faster on these small boxes)")
+    levels = otree.cluster_tree(n, leaf)
+    with threadpoolctl.threadpool_limits(1):
+        orc = ohbs.compress(levels, k, Om, Y, Ps, Z)
+    G = inputs.probes(rs[inputs.STREAM_PROBES], n, 8)
+    OG, OtG = ohbs.apply(orc, G), ohbs.apply(orc, G, transpose=True)
+    tree = hbs.Tree(n, leaf)
+    for path, bound in (("fp64", 1e-12), ("split", 1e-10)):
+        f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z), precision=path)
+        f.check()
+        e = rel(f.apply(dev(G)).cpu().numpy(), OG)
+        et = rel(f.apply(dev(G), transpose=True).cpu().numpy(), OtG)
+        progress(f"[fullsize] log kernel N={n} {path}: GPU vs oracle {e:.3e} (transpose {et:.3e})")
+        assert e <= bound and et <= bound
+        del f
