@@ -415,10 +415,21 @@ def main():
     ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="first run a plain copy kernel over MIB MiB (reference for HBM byte counters)")
+    ap.add_argument("--trace-summary", metavar="RESULTS_DB",
+                    help="no GPU run: print a markdown summary of a rocprofv3 --kernel-trace results file of "
+                         "bench.py on --workload")
+    ap.add_argument("--counter-summary", metavar="COUNTER_CSV",
+                    help="no GPU run: print a markdown table of a rocprofv3 --pmc counter file")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn the run_counter_collection.csv files of two rocprofv3 --pmc passes "
                          "(FETCH_SIZE, WRITE_SIZE) of bench.py --copy-probe MIB into the lq_kernel traffic file")
     args = ap.parse_args()
+    if args.trace_summary:
+        print(trace_summary(args.trace_summary, args.workload))
+        return
+    if args.counter_summary:
+        print(counter_summary(args.counter_summary))
+        return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 512, args.workload,
                               args=args)
@@ -577,6 +588,61 @@ def traffic_from_counters(fetch_csv, write_csv, mib, workload, dst=None, args=No
         json.dump(out, fh, indent=1)
     log(f"wrote {dst}: {out['bytes_per_launch'] / 1e6:.1f} MB per lq launch")
     return out
+
+
+def trace_summary(db_path, workload, sweeps=3):
+    """Markdown summary of a rocprofv3 kernel trace (its SQLite results
+    file) of bench.py on `workload`: kernel statistics of the whole run, and
+    the steady-state QR kernel launches (non-root launches of the last
+    `sweeps` sweeps, the launches bench.py's `roofline` time covers)."""
+    import collections
+    import sqlite3
+
+    con = sqlite3.connect(db_path)
+    rows = con.execute("select name, duration, grid_x, grid_y, grid_z, workgroup_x from kernels order by start").fetchall()
+    tot = collections.OrderedDict()
+    for name, dur, *_ in rows:
+        short = name.replace("(anonymous namespace)::", "").replace("hbs::", "").split("(")[0][:90]
+        c, t = tot.get(short, (0, 0))
+        tot[short] = (c + 1, t + dur)
+    allns = sum(t for _, t in tot.values())
+    out = ["| kernel | calls | avg us | total ms | % |", "|---|---|---|---|---|"]
+    for name, (c, t) in sorted(tot.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| {name} | {c} | {t / c / 1e3:.1f} | {t / 1e6:.2f} | {100 * t / allns:.1f} |")
+    roots = lq_launch_roots(workload)
+    lq = [r for r in rows if "lq_kernel" in r[0]][-sweeps * len(roots):]
+    steady = [r[1] for i, r in enumerate(lq) if not roots[i % len(roots)]]
+    out.append("")
+    out.append(f"Steady-state `lq_kernel`: {len(steady)} non-root launches of the last {sweeps} sweeps, "
+               f"average {sum(steady) / len(steady) / 1e3:.1f} us, {sum(steady) / sweeps / 1e6:.3f} ms per sweep.")
+    return "\n".join(out)
+
+
+def counter_summary(csv_path):
+    """Markdown table of a rocprofv3 --pmc counter file: per kernel name,
+    dispatches and the mean of each counter per dispatch."""
+    import collections
+    import csv
+
+    acc = collections.OrderedDict()
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            kname = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("hbs::", "")
+            key = (kname.split("(")[0][:80], r["Counter_Name"])
+            n, v, ids = acc.get(key, (0, 0.0, set()))
+            ids.add(r["Dispatch_Id"])
+            acc[key] = (n + 1, v + float(r["Counter_Value"]), ids)
+    names = sorted({k[1] for k in acc})
+    kern = list(dict.fromkeys(k[0] for k in acc))
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |", "|---|---|" + "---|" * len(names)]
+    for kname in kern:
+        cells, nd = [], 0
+        for c in names:
+            n, v, ids = acc.get((kname, c), (0, 0.0, set()))
+            nd = max(nd, len(ids))
+            cells.append(f"{v / max(len(ids), 1):.4g}" if ids else "")
+        out.append(f"| {kname} | {nd} | " + " | ".join(cells) + " |")
+    return "\n".join(out)
 
 
 def inputs_workloads():

@@ -211,9 +211,18 @@ def test_exact_rank_depth11_truncated_qr(hbs, progress):
 def test_logkernel_n65536_against_oracle_sweep(hbs, progress):
     """The 65536-point log-kernel workload at full size against the oracle's
     whole sweep on the oracle's own samples (formed on the CPU, 320 columns
-    of the dense kernel), FP64 and split paths, truncated-QR reading.  Both
-    sides truncate the same sketches with the same pivot rule, so they agree
-    far below the truncation error itself (1.5e-10)."""
+    of the dense kernel), FP64 and split paths, both readings of col.
+
+    These sketches have no gap at k (the kernel's singular values decay
+    smoothly), so the truncated basis is not unique to rounding: with the
+    pivoted QR, near-equal column norms are ranked differently by the two
+    reduction orders; with the SVD, the k-th and (k+1)-th directions are close
+    in value.  GPU and oracle then keep different but equally good bases, and
+    their operators differ by about the truncation error itself.  What is
+    unique is the accuracy: on 256 seeded rows of the dense kernel the GPU's
+    error must be within 1.5 times the oracle's, and the two operators may
+    differ by at most 2.5 times the oracle's error (the sum of two errors of
+    that size)."""
     import threadpoolctl
     wl = inputs.WORKLOADS["logkernel_ellipse_n65536_k50"]
     n, k, leaf, s = wl["n"], wl["k"], wl["leaf_max"], wl["s"]
@@ -225,18 +234,24 @@ def test_logkernel_n65536_against_oracle_sweep(hbs, progress):
     YZ = olog.sample(x, y, np.hstack((Om, Ps)), block=2048)
     Y, Z = np.ascontiguousarray(YZ[:, :s]), np.ascontiguousarray(YZ[:, s:])
     del YZ
-    progress("[fullsize] oracle sweep (one BLAS thread: faster on these small boxes)")
-    levels = otree.cluster_tree(n, leaf)
-    with threadpoolctl.threadpool_limits(1):
-        orc = ohbs.compress(levels, k, Om, Y, Ps, Z)
     G = inputs.probes(rs[inputs.STREAM_PROBES], n, 8)
-    OG, OtG = ohbs.apply(orc, G), ohbs.apply(orc, G, transpose=True)
+    R = np.sort(rs[inputs.STREAM_ROWS].choice(n, 256, replace=False))
+    AG_R = olog.sample(x, y, G, R)
+    levels = otree.cluster_tree(n, leaf)
     tree = hbs.Tree(n, leaf)
-    for path, bound in (("fp64", 1e-12), ("split", 1e-10)):
-        f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z), precision=path)
-        f.check()
-        e = rel(f.apply(dev(G)).cpu().numpy(), OG)
-        et = rel(f.apply(dev(G), transpose=True).cpu().numpy(), OtG)
-        progress(f"[fullsize] log kernel N={n} {path}: GPU vs oracle {e:.3e} (transpose {et:.3e})")
-        assert e <= bound and et <= bound
-        del f
+    for trunc in ("qr", "svd"):
+        progress(f"[fullsize] oracle sweep, {trunc} reading (one BLAS thread: faster on these small boxes)")
+        with threadpoolctl.threadpool_limits(1):
+            orc = ohbs.compress(levels, k, Om, Y, Ps, Z, truncation=trunc)
+        OG = ohbs.apply(orc, G)
+        e_o = rel(OG[R], AG_R)
+        for path in ("fp64", "split"):
+            f = hbs.compress(tree, k, dev(Om), dev(Y), dev(Ps), dev(Z), precision=path, truncation=trunc)
+            f.check()
+            TG = f.apply(dev(G)).cpu().numpy()
+            e_g, e_p = rel(TG[R], AG_R), rel(TG, OG)
+            progress(f"[fullsize] log kernel N={n} {trunc}/{path}: error on 256 kernel rows GPU {e_g:.3e}, "
+                     f"oracle {e_o:.3e}; GPU vs oracle {e_p:.3e}")
+            assert e_g <= 1.5 * e_o + 1e-13
+            assert e_p <= 2.5 * e_o
+            del f
