@@ -420,6 +420,8 @@ def main():
                          "bench.py on --workload")
     ap.add_argument("--counter-summary", metavar="COUNTER_CSV",
                     help="no GPU run: print a markdown table of a rocprofv3 --pmc counter file")
+    ap.add_argument("--traffic-out", metavar="JSON", default=None,
+                    help="with --traffic-from: write the traffic file here instead of profiles/")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="no GPU run: turn the run_counter_collection.csv files of two rocprofv3 --pmc passes "
                          "(FETCH_SIZE, WRITE_SIZE) of bench.py --copy-probe MIB into the lq_kernel traffic file")
@@ -432,7 +434,7 @@ def main():
         return
     if args.traffic_from:
         traffic_from_counters(args.traffic_from[0], args.traffic_from[1], args.copy_probe or 512, args.workload,
-                              args=args)
+                              dst=args.traffic_out, args=args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -596,6 +598,7 @@ def trace_summary(db_path, workload, sweeps=3):
     the steady-state QR kernel launches (non-root launches of the last
     `sweeps` sweeps, the launches bench.py's `roofline` time covers)."""
     import collections
+    import re
     import sqlite3
 
     con = sqlite3.connect(db_path)
@@ -615,6 +618,44 @@ def trace_summary(db_path, workload, sweeps=3):
     out.append("")
     out.append(f"Steady-state `lq_kernel`: {len(steady)} non-root launches of the last {sweeps} sweeps, "
                f"average {sum(steady) / len(steady) / 1e3:.1f} us, {sum(steady) / sweeps / 1e6:.3f} ms per sweep.")
+    # every sweep kernel of the last `sweeps` sweeps, by step of the sweep
+    # (a step starts at its QR-kernel launch)
+    kinds = ("lq_kernel", "col_kernel", "tail_a_kernel", "tail_b_kernel", "tail_c_kernel")
+    sw = [r for r in rows if any(k in r[0] for k in kinds)]
+    first = next(i for i in range(len(sw)) if sw[i] is lq[0])
+    per_step = collections.defaultdict(lambda: collections.defaultdict(list))
+    boxes = {}
+    step = -1
+    for name, dur, gx, gy, gz, wx in sw[first:]:
+        kind = next(k for k in kinds if k in name)
+        if kind == "lq_kernel":
+            step += 1
+        if step >= sweeps * len(roots):
+            break
+        st = step % len(roots)
+        if kind == "lq_kernel":
+            boxes[st] = gx // max(wx, 1)
+        targs = re.search(r"col_kernel<([^>]*)>", name)
+        if targs and targs.group(1).replace(" ", "").split(",")[-1] == "2":
+            kind = "col_kernel (Jacobi)"
+        per_step[st][kind].append(dur)
+    cols = ["lq_kernel", "col_kernel", "col_kernel (Jacobi)", "tail_a_kernel", "tail_b_kernel", "tail_c_kernel"]
+    cols = [c for c in cols if any(c in d for d in per_step.values())]
+    out.append("")
+    out.append(f"Per step of the sweep (average over the last {sweeps} sweeps, us; a step is one aligned level "
+               f"of one (k, s) class; boxes from the QR kernel's grid):")
+    out.append("")
+    out.append("| step | boxes | root | " + " | ".join(c.replace("_kernel", "") for c in cols) + " | sum |")
+    out.append("|---|---|---|" + "---|" * (len(cols) + 1))
+    tot = collections.defaultdict(float)
+    for st in sorted(per_step):
+        d = per_step[st]
+        vals = [sum(d[c]) / sweeps / 1e3 if c in d else 0.0 for c in cols]
+        for c, v in zip(cols, vals):
+            tot[c] += v
+        out.append(f"| {st} | {boxes.get(st, '')} | {'yes' if roots[st] else ''} | "
+                   + " | ".join(f"{v:.1f}" if v else "" for v in vals) + f" | {sum(vals):.1f} |")
+    out.append("| all | | | " + " | ".join(f"{tot[c]:.1f}" for c in cols) + f" | {sum(tot.values()):.1f} |")
     return "\n".join(out)
 
 

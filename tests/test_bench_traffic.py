@@ -70,3 +70,53 @@ def test_traffic_summary_needs_the_copy_probe(tmp_path):
                         Counter_Value=1.0))
     with pytest.raises(SystemExit):
         bench.traffic_from_counters(str(f_csv), str(f_csv), 512, "hbs_exact_n1024_k16", dst=str(tmp_path / "t.json"))
+
+
+def test_trace_summary_per_step(tmp_path):
+    """bench.py --trace-summary on a synthetic rocpd kernels table: the
+    per-step table of the last sweeps averages each kernel's duration by step
+    of the sweep, tells the Jacobi pass of col apart, and leaves out the
+    tuning launches and everything after the last sweep."""
+    import sqlite3
+
+    wl = "hbs_exact_n1024_k16"  # 5 levels below the root, then the root
+    per = 6
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table kernels (name text, duration int, grid_x int, grid_y int, grid_z int, "
+                "workgroup_x int, start int)")
+    rows = []
+
+    def launch(name, dur, boxes=1):
+        rows.append((name, dur, boxes * 256, 2, 1, 256, len(rows)))
+
+    lq = "void hbs::(anonymous namespace)::lq_kernel<256, 4, 1, 1, 16, 0>(hbs::SweepArgs)"
+    col1 = "void hbs::(anonymous namespace)::col_kernel<256, 4, 1, 8, 0, 1>(hbs::SweepArgs)"
+    col2 = "void hbs::(anonymous namespace)::col_kernel<256, 4, 1, 8, 0, 2>(hbs::SweepArgs)"
+    for sw in range(5):  # sweeps 0 and 1 are tuning / warm-up with other durations
+        for j in range(per):
+            scale = 1000 if sw < 2 else 1
+            launch(lq, scale * (1000 * (j + 1) + 1000 * sw), boxes=2 ** (per - 1 - j))
+            if j == per - 1:
+                break
+            launch(col1, scale * 2000)
+            launch(col2, scale * 300)
+            for t in ("tail_a_kernel<0, 2>", "tail_b_kernel<16>", "tail_c_kernel<0, 2>"):
+                launch(f"void hbs::(anonymous namespace)::{t}(hbs::SweepArgs)", scale * 500)
+    launch("apply_up_kernel", 10 ** 9)  # after the sweeps: not part of any step
+    con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    md = bench.trace_summary(str(db), wl, sweeps=3)
+    table = md.split("Per step of the sweep")[1].splitlines()
+    head = [c.strip() for c in table[2].split("|")[1:-1]]
+    assert head == ["step", "boxes", "root", "lq", "col", "col (Jacobi)", "tail_a", "tail_b", "tail_c", "sum"]
+    body = [[c.strip() for c in ln.split("|")[1:-1]] for ln in table[4:4 + per]]
+    for j, r in enumerate(body):
+        assert int(r[0]) == j and int(r[1]) == 2 ** (per - 1 - j)
+        assert (r[2] == "yes") == (j == per - 1)
+        assert float(r[3]) == pytest.approx((1000 * (j + 1) + 1000 * 3) / 1e3)  # mean of sweeps 2, 3, 4
+        if j < per - 1:
+            assert [float(x) for x in r[4:9]] == pytest.approx([2.0, 0.3, 0.5, 0.5, 0.5])
+        else:
+            assert r[4:9] == [""] * 5
