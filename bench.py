@@ -692,10 +692,15 @@ def inputs_workloads():
 
 
 def _side_digest():
+    """Digest of the QR kernel's source: hbs_side.hip up to the column
+    kernel's section (the shared helpers, LqCore and lq_kernel), so that a
+    change to the column kernel alone keeps the traffic file valid."""
     import hashlib
     p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2205_02990_amd", "csrc", "hbs_side.hip")
     with open(p, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+        text = fh.read()
+    end = text.find(b"// col kernel:")
+    return hashlib.sha256(text if end < 0 else text[:end]).hexdigest()[:16]
 
 
 if __name__ == "__main__":

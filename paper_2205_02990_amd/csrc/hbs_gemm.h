@@ -252,6 +252,50 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
         }
         __syncthreads();
       }
+      // recombine the S diagonal sums of column block b and store them
+      auto finish = [&](int b, const gemm_i4 (&ac)[S]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ti = rb + 4 * lk + r, tj = cb + 16 * b + li;
+          const int gi = i0 + ti, gj = j0 + tj;
+          if (gi < M && gj < N) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = S - 1; d >= 0; --d) v += ldexp((double)ac[d][r], -7 * (d + 2));
+            v = alpha * ldexp(v, sm.ea[ti] + sm.eb[tj]);
+            C[gi * ldc + gj] = (beta != 0.0) ? beta * C0[gi * ldc0 + gj] + v : v;
+          }
+        }
+      };
+      if constexpr (KCH == 1) {
+        // one chunk: the two column blocks one after the other, so that only
+        // one block's S diagonal sums are live (half the accumulator
+        // registers, twice the workgroups per compute unit)
+        slice_regs<S>(xa[0], c, g, sm.ea[c], sm.u.q.As);
+        slice_regs<S>(xb[0], c, g, sm.eb[c], sm.u.q.Bs);
+        __syncthreads();
+        gemm_i4 ap[S];
+        const int wa = slice_word(rb + li, 4 * lk);
+#pragma unroll
+        for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.As[p][rb + li][wa]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          gemm_i4 ac[S];
+#pragma unroll
+          for (int d = 0; d < S; ++d) ac[d] = gemm_i4{0, 0, 0, 0};
+          const int wb = slice_word(cb + 16 * b + li, 4 * lk);
+#pragma unroll
+          for (int q = 0; q < S; ++q) {
+            const gemm_i4 bq = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
+#pragma unroll
+            for (int p = 0; p + q < S; ++p)
+              ac[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq, ac[p + q], 0, 0, 0);
+          }
+          finish(b, ac);
+        }
+        __syncthreads();
+        continue;
+      }
       gemm_i4 acc[2][S];
 #pragma unroll
       for (int b = 0; b < 2; ++b)
@@ -269,32 +313,288 @@ __device__ __forceinline__ void sliced_lt(int M, int N, int K, double alpha, con
         for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.As[p][rb + li][wa]);
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          gemm_i4 bq[S];
           const int wb = slice_word(cb + 16 * b + li, 4 * lk);
 #pragma unroll
-          for (int q = 0; q < S; ++q) bq[q] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
+          for (int q = 0; q < S; ++q) {
+            const gemm_i4 bq = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
 #pragma unroll
-          for (int p = 0; p < S; ++p)
-#pragma unroll
-            for (int q = 0; p + q < S; ++q)
-              acc[b][p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq[q], acc[b][p + q], 0, 0, 0);
+            for (int p = 0; p + q < S; ++p)
+              acc[b][p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq, acc[b][p + q], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);  // one right-operand slice live at a time
+          }
         }
         __syncthreads();
       }
 #pragma unroll
+      for (int b = 0; b < 2; ++b) finish(b, acc[b]);
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The parent blocks one side of a box hands up (eq. omega_tau_and_y_tau), for
+// one tile of nc <= 64 columns of s:
+//   top = B1^* P0,   bot = B3^* P1 - B2^* P0     (k x nc each, row stride ldo)
+// with B1, B2, B3 m x k (row stride k) and P0, P1 m x nc (row stride ld).  It
+// is one product with 2k output rows over two blocks of contracted indices:
+// block 0 runs over the rows of P0 with left operand [B1 | -B2], block 1 over
+// the rows of P1 with [0 | B3].  Each panel is read (and, split, sliced) once
+// for both of its products.
+struct ParentOp {
+  const double *B1, *B2, *B3, *P0, *P1;
+  int64_t ld;
+  double *top, *bot;
+  int64_t ldo;
+  int m, k, nc;
+};
+
+// Where row i of block b's left operand L^T comes from: the entries
+// L^T(i, kk) = sgn * src[kk * k] for kk < m (sgn = 0: a zero row).  Chosen
+// once per thread and block from values already in registers.
+struct ParentRow {
+  const double* src;
+  double sgn;
+};
+__device__ __forceinline__ ParentRow parent_row(int b, int i, int k, const double* B1, const double* B2,
+                                                const double* B3) {
+  const bool lo = i < k;
+  const double* base = b ? B3 : (lo ? B1 : B2);
+  return ParentRow{base + (lo ? i : i - k), b ? (lo ? 0.0 : 1.0) : (lo ? 1.0 : -1.0)};
+}
+
+// FP64: the product on v_mfma_f64_16x16x4f64, tiled as mfma_gemm (64 x 64
+// output tiles, K staged in chunks of TK); block 1 starts at the contracted
+// index mp = m rounded up to TK, so that no chunk mixes the blocks and the
+// waves whose rows are the zero rows of block 1 skip its products.
+template <int TK, int NT = kGemmThreads>
+__device__ __forceinline__ void parent_mfma(const ParentOp& o, MfmaSmem<TK>& sm) {
+  static_assert(TK % 4 == 0 && (NT == 256 || NT == 512), "tile");
+  constexpr int LA = 64 * TK / NT;
+  constexpr int TR = (NT == 256) ? 2 : 1;
+  const double *B1 = o.B1, *B2 = o.B2, *B3 = o.B3, *P0 = o.P0, *P1 = o.P1;
+  const int64_t ld = o.ld;
+  const int m = o.m, k = o.k, M = 2 * k, N = o.nc;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rb = (wv >> 1) * 16 * TR, cb = (wv & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  const int mp = (m + TK - 1) / TK * TK, K = mp + m;
+  // staging: element idx = tid + r NT of a chunk is output index idx % 64 =
+  // tid % 64 (the same for every r) and contracted index k0 + idx / 64;
+  // both operands are contiguous along the output index
+  const int ii = tid & 63;
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    gemm_d4 acc[TR][2];
+#pragma unroll
+    for (int a = 0; a < TR; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = gemm_d4{0.0, 0.0, 0.0, 0.0};
+    const bool oki = i0 + ii < M, okj = ii < N;
+    double pa[LA], pb[LA];
+    auto fetch = [&](int k0) {
+      const int blk = k0 >= mp;
+      const ParentRow lr = parent_row(blk, oki ? i0 + ii : 0, k, B1, B2, B3);
+      const double* P = (blk ? P1 : P0) + ii;
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        const int kk = k0 - blk * mp + (tid + r * NT) / 64;
+        const bool oka = oki && kk < m, okb = okj && kk < m;
+        const double v = lr.src[oka ? (int64_t)kk * k : 0];
+        const double w = P[okb ? (int64_t)kk * ld : 0];
+        pa[r] = oka ? lr.sgn * v : 0.0;
+        pb[r] = okb ? w : 0.0;
+      }
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < K; k0 += TK) {
+#pragma unroll
+      for (int r = 0; r < LA; ++r) {
+        const int idx = tid + r * NT;
+        sm.As[idx / 64][ii] = pa[r];
+        sm.Bs[idx / 64][ii] = pb[r];
+      }
+      __syncthreads();
+      if (k0 + TK < K) fetch(k0 + TK);  // block 0's chunks end at mp, where block 1's begin
+      const bool blk1 = k0 >= mp;
+#pragma unroll
+      for (int kk = 0; kk < TK; kk += 4) {
+        const double b0 = sm.Bs[kk + lk][cb + li], b1 = sm.Bs[kk + lk][cb + 16 + li];
+#pragma unroll
+        for (int a = 0; a < TR; ++a) {
+          const int r0 = i0 + rb + 16 * a;
+          // wave-uniform: rows past the output, or block 1's zero rows
+          if (r0 >= M || (blk1 && r0 + 16 <= k)) continue;
+          const double av = sm.As[kk + lk][rb + 16 * a + li];
+          acc[a][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, acc[a][0], 0, 0, 0);
+          acc[a][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, acc[a][1], 0, 0, 0);
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < TR; ++a)
+#pragma unroll
       for (int b = 0; b < 2; ++b)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int ti = rb + 4 * lk + r, tj = cb + 16 * b + li;
-          const int gi = i0 + ti, gj = j0 + tj;
+          const int gi = i0 + rb + 16 * a + lk + 4 * r, gj = cb + 16 * b + li;
           if (gi < M && gj < N) {
-            double v = 0.0;
-#pragma unroll
-            for (int d = S - 1; d >= 0; --d) v += ldexp((double)acc[b][d][r], -7 * (d + 2));
-            v = alpha * ldexp(v, sm.ea[ti] + sm.eb[tj]);
-            C[gi * ldc + gj] = (beta != 0.0) ? beta * C0[gi * ldc0 + gj] + v : v;
+            double* dst = (gi < k) ? o.top + (int64_t)gi * o.ldo : o.bot + (int64_t)(gi - k) * o.ldo;
+            dst[gj] = acc[a][b][r];
           }
         }
+  }
+  __syncthreads();
+}
+
+// Split precision: the same product with both operands cut into S slices as
+// in sliced_lt, every block with scales of its own (the rows of P0 and P1,
+// and of the left operand's blocks, may differ in magnitude by any amount),
+// each block's exact integer sums recombined in FP64 and the two blocks
+// added in FP64.  Called by the 512 threads of a workgroup (8 waves, each a
+// 16 x 32 strip of a 64 x 64 output tile); K = m <= KCH kSliceK per block.
+template <int S, int KCH = kSliceChunks>
+__device__ __forceinline__ void parent_sliced(const ParentOp& o, SliceSmem<S>& sm) {
+  const double *B1 = o.B1, *B2 = o.B2, *B3 = o.B3, *P0 = o.P0, *P1 = o.P1;
+  const int64_t ld = o.ld;
+  const int m = o.m, k = o.k, M = 2 * k, N = o.nc;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int rb = (wv >> 1) * 16, cb = (wv & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  const int c = tid & 63, g = tid >> 6;  // staging: output index c, contracted group g
+  for (int i0 = 0; i0 < M; i0 += 64) {
+    const bool wave_rows = i0 + rb < M;  // wave-uniform: some of this wave's rows are output rows
+    const bool oki = i0 + c < M, okj = c < N;
+#pragma unroll 1
+    for (int blk = 0; blk < 2; ++blk) {
+      const ParentRow lr = parent_row(blk, oki ? i0 + c : 0, k, B1, B2, B3);
+      const double* P = (blk ? P1 : P0) + c;
+      // this thread's values of chunk h (masked), and their largest magnitudes
+      double xa[kSlicePer], xb[kSlicePer];
+      auto load = [&](int h) {
+#pragma unroll
+        for (int u = 0; u < kSlicePer; ++u) {
+          const int kk = kSliceK * h + kSlicePer * g + u;
+          const bool oka = oki && kk < m, okb = okj && kk < m;
+          const double va = lr.src[oka ? (int64_t)kk * k : 0];
+          const double vb = P[okb ? (int64_t)kk * ld : 0];
+          xa[u] = oka ? lr.sgn * va : 0.0;
+          xb[u] = okb ? vb : 0.0;
+        }
+      };
+      double ma = 0.0, mb = 0.0;
+#pragma unroll
+      for (int h = KCH - 1; h >= 0; --h) {
+        // the scales span every chunk; chunk 0's values stay loaded for its slicing
+        load(h);
+#pragma unroll
+        for (int u = 0; u < kSlicePer; ++u) {
+          ma = fmax(ma, fabs(xa[u]));
+          mb = fmax(mb, fabs(xb[u]));
+        }
+      }
+      sm.u.red[0][g][c] = ma;
+      sm.u.red[1][g][c] = mb;
+      __syncthreads();
+      if (tid < 128) {
+        const int h = tid >> 6;
+        double mx = 0.0;
+#pragma unroll
+        for (int q = 0; q < kSliceGroups; ++q) mx = fmax(mx, sm.u.red[h][q][c]);
+        int e = 0;
+        (void)frexp(mx, &e);
+        (h ? sm.eb : sm.ea)[c] = e;
+      }
+      __syncthreads();
+      // this wave's rows take part in this block (block 1's first k rows are zero)
+      const bool live = wave_rows && !(blk == 1 && i0 + rb + 16 <= k);
+      // recombine this block's exact sums of column block b and store them
+      // (block 0) or add them to what block 0 stored (block 1; the same lane)
+      auto gather = [&](int b, const gemm_i4 (&ac)[S]) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ti = rb + 4 * lk + r, tj = cb + 16 * b + li;
+          const int gi = i0 + ti;
+          if (gi < M && tj < N) {
+            double v = 0.0;
+#pragma unroll
+            for (int d = S - 1; d >= 0; --d) v += ldexp((double)ac[d][r], -7 * (d + 2));
+            v = ldexp(v, sm.ea[ti] + sm.eb[tj]);
+            double* dst = (gi < k) ? o.top + (int64_t)gi * o.ldo : o.bot + (int64_t)(gi - k) * o.ldo;
+            dst[tj] = blk ? dst[tj] + v : v;
+          }
+        }
+      };
+      if constexpr (KCH == 1) {
+        slice_regs<S>(xa, c, g, sm.ea[c], sm.u.q.As);
+        __builtin_amdgcn_sched_barrier(0);
+        slice_regs<S>(xb, c, g, sm.eb[c], sm.u.q.Bs);
+        __syncthreads();
+        if (live) {
+          gemm_i4 ap[S];
+          const int wa = slice_word(rb + li, 4 * lk);
+#pragma unroll
+          for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.As[p][rb + li][wa]);
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            gemm_i4 ac[S];
+#pragma unroll
+            for (int d = 0; d < S; ++d) ac[d] = gemm_i4{0, 0, 0, 0};
+            const int wb = slice_word(cb + 16 * b + li, 4 * lk);
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+              const gemm_i4 bq = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
+#pragma unroll
+              for (int p = 0; p + q < S; ++p)
+                ac[p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq, ac[p + q], 0, 0, 0);
+              // one slice of the right operand live at a time (the scheduler
+              // would otherwise load all S ahead and exceed 128 registers)
+              __builtin_amdgcn_sched_barrier(0);
+            }
+            gather(b, ac);
+          }
+        }
+      } else {
+        gemm_i4 acc[2][S];
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int d = 0; d < S; ++d) acc[b][d] = gemm_i4{0, 0, 0, 0};
+#pragma unroll
+        for (int h = 0; h < KCH; ++h) {
+          if (kSliceK * h >= m) break;
+          if (h > 0) {
+            __syncthreads();  // every wave has read the previous chunk's slices
+            load(h);
+          }
+          slice_regs<S>(xa, c, g, sm.ea[c], sm.u.q.As);
+          slice_regs<S>(xb, c, g, sm.eb[c], sm.u.q.Bs);
+          __syncthreads();
+          if (live) {
+            gemm_i4 ap[S];
+            const int wa = slice_word(rb + li, 4 * lk);
+#pragma unroll
+            for (int p = 0; p < S; ++p) ap[p] = *reinterpret_cast<const gemm_i4*>(&sm.u.q.As[p][rb + li][wa]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              const int wb = slice_word(cb + 16 * b + li, 4 * lk);
+#pragma unroll
+              for (int q = 0; q < S; ++q) {
+                const gemm_i4 bq = *reinterpret_cast<const gemm_i4*>(&sm.u.q.Bs[q][cb + 16 * b + li][wb]);
+#pragma unroll
+                for (int p = 0; p + q < S; ++p)
+                  acc[b][p + q] = __builtin_amdgcn_mfma_i32_16x16x64_i8(ap[p], bq, acc[b][p + q], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);  // one right-operand slice live at a time
+              }
+            }
+          }
+        }
+        if (live) {
+#pragma unroll
+          for (int b = 0; b < 2; ++b) gather(b, acc[b]);
+        }
+      }
+      // the slices and scales are rewritten by the next block: every wave has used them
       __syncthreads();
     }
   }

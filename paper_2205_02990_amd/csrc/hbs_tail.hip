@@ -10,15 +10,15 @@
 //   U^* D = U^* W - T = E^*,         so U^* (Y - D Omega) = U^* Y - E^* Omega,
 //   D V   = W V - U U^* W V =: H,    so V^* (Z - D^* Psi) = V^* Z - H^* Psi,
 // and the parent blocks no longer wait for D.  Three launches per level:
-//   tail_a  F = X U, Q = W V, T0 = U^* W, and the bulk blocks V^* Omega,
-//           U^* Y, U^* Psi, V^* Z (written to the parent panels);
+//   tail_a  F = X U, Q = W V, T0 = U^* W;
 //   tail_b  G = V^* F, G2 = U^* Q, E = F - V G, H = Q - U G2, T = T0 - E^*
 //           (two chains, split by rows);
-//   tail_c  D = W - U T, and the parent blocks' corrections - E^* Omega,
-//           - H^* Psi.
-// The bulk blocks (every product with a test or sample panel) run in FP64
-// on the matrix cores, or split-precision (sliced_lt) when the batch asks
-// for it; everything that forms D stays FP64.
+//   tail_c  D = W - U T, and the parent blocks, one product per side and
+//           64-column tile of s: Omega' = V^* Omega with Y' = U^* Y - E^* Omega,
+//           Psi' = U^* Psi with Z' = V^* Z - H^* Psi (each panel read once).
+// The parent blocks (every product with a test or sample panel) run in FP64
+// on the matrix cores, or split-precision (parent_sliced) when the batch
+// asks for it; everything that forms D stays FP64.
 #include "hbs_gemm.h"
 #include "hbs_internal.h"
 
@@ -84,15 +84,25 @@ inline dim3 xcd_grid(int nboxes, int ny) {
   return dim3((unsigned)gx, (unsigned)((total + gx - 1) / gx));
 }
 
-// C = alpha L^T R + beta C0 for a basis L (K x M, row stride ldl) and a panel R.
+// The parent blocks of one side of a box for one 64-column tile of s.  Split
+// products over boxes of more than 64 rows (two staging chunks) run as three
+// separate products (P0 sliced twice): the fused product with two chunks
+// needs more than the 256 registers a lane can have.
 template <int S, int KCH>
-__device__ __forceinline__ void bulk(TailSmem<S>& sm, int M, int N, int K, double alpha, const double* L, int64_t ldl,
-                            const double* R, int64_t ldr, double beta, const double* C0, int64_t ldc0, double* C,
-                            int64_t ldc) {
-  if constexpr (S > 0)
-    sliced_lt<S, KCH>(M, N, K, alpha, L, ldl, R, ldr, beta, C0, ldc0, C, ldc, sm.sl);
-  else
-    mfma_gemm<16>(M, N, K, alpha, L, 1, ldl, R, ldr, 1, beta, C0, ldc0, C, ldc, sm.g);
+__device__ __forceinline__ void parent(TailSmem<S>& sm, const ParentOp& op) {
+  if constexpr (S > 0 && KCH > 1) {
+    // (the scheduling barriers keep each product's loads from being hoisted
+    // into the one before, which would exceed the register file)
+    sliced_lt<S, KCH>(op.k, op.nc, op.m, 1.0, op.B1, op.k, op.P0, op.ld, 0.0, nullptr, 0, op.top, op.ldo, sm.sl);
+    __builtin_amdgcn_sched_barrier(0);
+    sliced_lt<S, KCH>(op.k, op.nc, op.m, 1.0, op.B3, op.k, op.P1, op.ld, 0.0, nullptr, 0, op.bot, op.ldo, sm.sl);
+    __builtin_amdgcn_sched_barrier(0);
+    sliced_lt<S, KCH>(op.k, op.nc, op.m, -1.0, op.B2, op.k, op.P0, op.ld, 1.0, op.bot, op.ldo, op.bot, op.ldo, sm.sl);
+  } else if constexpr (S > 0) {
+    parent_sliced<S, KCH>(op, sm.sl);
+  } else {
+    parent_mfma<16>(op, sm.g);
+  }
 }
 
 // FP64 product by the workgroup of either tail variant
@@ -106,42 +116,34 @@ __device__ __forceinline__ void dgemm(TailSmem<S>& sm, int M, int N, int K, doub
 
 template <int S>
 constexpr int tail_threads() { return S > 0 ? kSliceThreads : kGemmThreads; }
+// the fewest waves per SIMD the register allocation must leave room for (0:
+// the compiler's choice): 4 for the one-chunk split products (at most 128
+// registers a lane), so that two of their 8-wave workgroups share a compute
+// unit and hide each other's slicing and barriers
+template <int S, int KCH>
+constexpr int tail_min_waves() { return 0; }
 
-// grid (boxes, 3 mt + 4 st): mt = row tiles of the box, st = 64-column tiles of s
-template <int S, int KCH = kSliceChunks>
-__global__ void __launch_bounds__(tail_threads<S>()) tail_a_kernel(SweepArgs a) {
-  __shared__ TailSmem<S> sm;
+// grid (boxes, 3 mt): mt = row tiles of the box; FP64 on both paths
+__global__ void __launch_bounds__(kGemmThreads) tail_a_kernel(SweepArgs a) {
+  __shared__ MfmaSmem<16> sm;
   const int mt = (a.mmax + 63) / 64;
-  const XcdTile tl = xcd_tile(3 * mt + 4 * ((a.s + 63) / 64));
+  const XcdTile tl = xcd_tile(3 * mt);
   if (tl.box >= a.nboxes) return;
   const BoxDesc& bx = a.box[tl.box];
-  const int m = bx.m, k = a.k, s = a.s, dld = bx.dld;
+  const int m = bx.m, k = a.k, dld = bx.dld;
   const int y = tl.y;
-  if (y >= 3 * mt) {
-    const int st = (s + 63) / 64;
-    const int q = y - 3 * mt, which = q / st, c0 = (q % st) * 64;
-    if (c0 >= s) return;
-    // which is the PanelKind: V^* Omega, U^* Y, U^* Psi, V^* Z
-    const PanelSrc& ps = a.src[bx.src];
-    const int64_t ld = ps.ld;
-    const bool useV = (which == kOm) || (which == kZ);
-    const double* L = useV ? bx.V : bx.U;
-    const double* P = ps.p[which] + bx.row0 * ld + c0;
-    bulk<S, KCH>(sm, k, min(64, s - c0), m, 1.0, L, k, P, ld, 0.0, nullptr, 0, bx.np[which] + c0, s);
-    return;
-  }
   const int which = y / mt, r0 = (y % mt) * 64;
   if (r0 >= m) return;
   const int nr = min(64, m - r0);
   TailWs ws(bx.T, dld, k);
   if (which == 0)  // F = X U (rows r0..)
-    dgemm<S>(sm, nr, k, m, 1.0, bx.X + (int64_t)r0 * dld, dld, 1, bx.U, k, 1, 0.0, nullptr, 0,
-                 ws.F + (int64_t)r0 * k, k);
+    mfma_gemm<16>(nr, k, m, 1.0, bx.X + (int64_t)r0 * dld, dld, 1, bx.U, k, 1, 0.0, nullptr, 0,
+                  ws.F + (int64_t)r0 * k, k, sm);
   else if (which == 1)  // Q = W V
-    dgemm<S>(sm, nr, k, m, 1.0, bx.W + (int64_t)r0 * dld, dld, 1, bx.V, k, 1, 0.0, nullptr, 0,
-                 ws.Q + (int64_t)r0 * k, k);
+    mfma_gemm<16>(nr, k, m, 1.0, bx.W + (int64_t)r0 * dld, dld, 1, bx.V, k, 1, 0.0, nullptr, 0,
+                  ws.Q + (int64_t)r0 * k, k, sm);
   else  // T0 = U^* W (columns r0..)
-    dgemm<S>(sm, k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld);
+    mfma_gemm<16>(k, nr, m, 1.0, bx.U, 1, k, bx.W + r0, dld, 1, 0.0, nullptr, 0, ws.T0 + r0, dld, sm);
 }
 
 // grid (boxes, 2 nrb): chain 0 forms G = V^* F, then rows of E = F - V G and
@@ -175,7 +177,7 @@ __global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
 
 // grid (boxes, mt^2 + 2 st)
 template <int S, int KCH = kSliceChunks>
-__global__ void __launch_bounds__(tail_threads<S>()) tail_c_kernel(SweepArgs a) {
+__global__ void __launch_bounds__(tail_threads<S>(), (tail_min_waves<S, KCH>())) tail_c_kernel(SweepArgs a) {
   __shared__ TailSmem<S> sm;
   const int mt = (a.mmax + 63) / 64;
   const XcdTile tl = xcd_tile(mt * mt + 2 * ((a.s + 63) / 64));
@@ -192,15 +194,25 @@ __global__ void __launch_bounds__(tail_threads<S>()) tail_c_kernel(SweepArgs a) 
     return;
   }
   const int st = (s + 63) / 64;
-  const int q = y - mt * mt, which = q / st, c0 = (q % st) * 64;
+  const int q = y - mt * mt, side = q / st, c0 = (q % st) * 64;
   if (c0 >= s) return;
   const PanelSrc& ps = a.src[bx.src];
-  const int64_t ld = ps.ld;
-  // which 0: Y' = U^* Y - E^* Omega;  which 1: Z' = V^* Z - H^* Psi (in place)
-  const double* L = which ? ws.H : ws.E;
-  const double* P = ps.p[2 * which] + bx.row0 * ld + c0;  // Omega or Psi
-  double* out = bx.np[2 * which + 1] + c0;                 // Y' or Z'
-  bulk<S, KCH>(sm, k, min(64, s - c0), m, -1.0, L, k, P, ld, 1.0, out, s, out, s);
+  // side 0: Omega' = V^* Omega, Y' = U^* Y - E^* Omega;
+  // side 1: Psi' = U^* Psi, Z' = V^* Z - H^* Psi
+  ParentOp op;
+  op.B1 = side ? bx.U : bx.V;
+  op.B2 = side ? ws.H : ws.E;
+  op.B3 = side ? bx.V : bx.U;
+  op.ld = ps.ld;
+  op.P0 = ps.p[2 * side] + bx.row0 * op.ld + c0;
+  op.P1 = ps.p[2 * side + 1] + bx.row0 * op.ld + c0;
+  op.top = bx.np[2 * side] + c0;
+  op.bot = bx.np[2 * side + 1] + c0;
+  op.ldo = s;
+  op.m = m;
+  op.k = k;
+  op.nc = min(64, s - c0);
+  parent<S, KCH>(sm, op);
 }
 
 }  // namespace
@@ -215,12 +227,6 @@ namespace {
 
 // the split-precision launch of tail_a or tail_c for S slices, with one
 // staging chunk when the boxes have at most kSliceK rows
-struct TailA {
-  template <int S, int KCH>
-  static void launch(dim3 grid, hipStream_t st, const SweepArgs& a) {
-    hipLaunchKernelGGL((tail_a_kernel<S, KCH>), grid, dim3(kSliceThreads), 0, st, a);
-  }
-};
 struct TailC {
   template <int S, int KCH>
   static void launch(dim3 grid, hipStream_t st, const SweepArgs& a) {
@@ -244,14 +250,11 @@ void launch_sliced(int slices, bool one_chunk, dim3 grid, hipStream_t st, const 
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st) {
   const int mt = (a.mmax + 63) / 64, sct = (a.s + 63) / 64;
   if (a.mixed && a.mmax > kSliceChunks * kSliceK) return hipErrorInvalidValue;  // split products contract over <= 128 rows
-  if (xcd_total(a.nboxes, 3 * mt + 4 * sct) >= ((int64_t)1 << 31)) return hipErrorInvalidValue;
+  if (xcd_total(a.nboxes, 3 * mt > mt * mt + 2 * sct ? 3 * mt : mt * mt + 2 * sct) >= ((int64_t)1 << 31))
+    return hipErrorInvalidValue;
   if (a.mixed && (a.slices < 6 || a.slices > 8)) return hipErrorInvalidValue;
   if (part == 0) {
-    const dim3 grid = xcd_grid(a.nboxes, 3 * mt + 4 * sct);
-    if (!a.mixed)
-      hipLaunchKernelGGL(tail_a_kernel<0>, grid, dim3(kGemmThreads), 0, st, a);
-    else
-      launch_sliced<TailA>(a.slices, a.mmax <= kSliceK, grid, st, a);
+    hipLaunchKernelGGL(tail_a_kernel, xcd_grid(a.nboxes, 3 * mt), dim3(kGemmThreads), 0, st, a);
   } else if (part == 1) {
     // few boxes: latency bound, row blocks in parallel and deeper K chunks
     if (variant < 0) variant = a.nboxes < 256 ? 1 : 0;
