@@ -523,8 +523,8 @@ hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
     if (tune_lookup(tune_key(dev, 1, a), &v)) {
       ln.col = v.first;
     } else {
-      int cand[16];
-      const int n = hbs::col_candidates(a, cmode, cand, 16);
+      int cand[32];
+      const int n = hbs::col_candidates(a, cmode, cand, 32);
       float best = 1e30f;
       for (int i = 0; i < n && e == hipSuccess; ++i) {
         float t = 0.0f;
@@ -539,8 +539,8 @@ hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
       if (tune_lookup(tune_key(dev, 3, a), &v)) {
         ln.colj = v.first;
       } else {
-        int cand[16];
-        const int n = hbs::col_candidates(a, 2, cand, 16);
+        int cand[32];
+        const int n = hbs::col_candidates(a, 2, cand, 32);
         float best = 1e30f;
         for (int i = 0; i < n && e == hipSuccess; ++i) {
           float t = 0.0f;
