@@ -408,6 +408,8 @@ def main():
     ap.add_argument("--path", default="both", choices=["both", "fp64", "split"],
                     help="both: the split-precision path gives `value`, the FP64 path runs beside it")
     ap.add_argument("--truncation", default="qr", choices=["qr", "svd"])
+    ap.add_argument("--slices", type=int, default=0, choices=[0, 6, 7, 8],
+                    help="split path: 7-bit slices per operand (0: the library's default, 8)")
     ap.add_argument("--n", type=int, default=0,
                     help="single-instance workloads: N other than the workload's own (same k, leaf, s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -451,6 +453,8 @@ def main():
         if wl["kind"] == "batch":
             raise SystemExit("--n applies to single-instance workloads")
         wl["n"] = args.n
+    if args.slices:
+        os.environ["HBS_SPLIT_SLICES"] = str(args.slices)  # read when a factor set or batch is created
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     hbs.load()
@@ -505,7 +509,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64+i8-slices" if paths[0] == "split" else "f64", "data": "synthetic",
         "config": {"workload": args.workload + (f" at N = {args.n}" if args.n else ""), **P.config,
-                   "path": paths[0], "truncation": args.truncation},
+                   "path": paths[0], "truncation": args.truncation,
+                   "slices": (args.slices or 8) if "split" in paths else None},
         "roofline": roofline,
         "rel_apply_err": head["rel_apply_err"], "power_rel_err": head["power_rel_err"],
         "paths": {p: strip(res[p]) for p in paths},

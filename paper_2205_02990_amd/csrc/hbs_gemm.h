@@ -23,7 +23,9 @@ typedef int gemm_i4 __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // FP64: C(i, j) = alpha * sum_kk A(i, kk) B(kk, j) + beta * C0(i, j), i < M,
 // j < N, with A(i, kk) = A[i * sar + kk * sac], B(kk, j) = B[kk * sbr + j * sbc]
-// (strides express transposes).  64 x 64 output tiles; with NT = 256 threads
+// (strides express transposes; all offsets within one box's blocks, so they
+// are 32-bit, which keeps the address arithmetic in fewer registers).  64 x 64
+// output tiles; with NT = 256 threads
 // each wave owns a 32 x 32 quarter (2 x 2 MFMA blocks of 16 x 16), with 512 a
 // 16 x 32 eighth (1 x 2 blocks).  K is staged through LDS
 // in chunks of TK with the next chunk's global loads in flight during the
@@ -38,9 +40,9 @@ struct MfmaSmem {
 };
 
 template <int TK, int NT = kGemmThreads>
-__device__ __forceinline__ void mfma_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int64_t sar,
-                          int64_t sac, const double* __restrict__ B, int64_t sbr, int64_t sbc, double beta,
-                          const double* C0, int64_t ldc0, double* C, int64_t ldc, MfmaSmem<TK>& sm) {
+__device__ __forceinline__ void mfma_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int sar,
+                                          int sac, const double* __restrict__ B, int sbr, int sbc, double beta,
+                                          const double* C0, int ldc0, double* C, int ldc, MfmaSmem<TK>& sm) {
   static_assert(TK % 4 == 0, "K chunk must be a multiple of the MFMA depth");
   static_assert(NT == 256 || NT == 512, "4 or 8 waves");
   constexpr int LA = 64 * TK / NT;

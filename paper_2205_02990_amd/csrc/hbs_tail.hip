@@ -107,9 +107,9 @@ __device__ __forceinline__ void parent(TailSmem<S>& sm, const ParentOp& op) {
 
 // FP64 product by the workgroup of either tail variant
 template <int S>
-__device__ __forceinline__ void dgemm(TailSmem<S>& sm, int M, int N, int K, double alpha, const double* A, int64_t sar,
-                             int64_t sac, const double* B, int64_t sbr, int64_t sbc, double beta, const double* C0,
-                             int64_t ldc0, double* C, int64_t ldc) {
+__device__ __forceinline__ void dgemm(TailSmem<S>& sm, int M, int N, int K, double alpha, const double* A, int sar,
+                                      int sac, const double* B, int sbr, int sbc, double beta, const double* C0,
+                                      int ldc0, double* C, int ldc) {
   mfma_gemm<16, (S > 0 ? kSliceThreads : kGemmThreads)>(M, N, K, alpha, A, sar, sac, B, sbr, sbc, beta, C0, ldc0, C,
                                                       ldc, sm.g);
 }
@@ -123,8 +123,9 @@ constexpr int tail_threads() { return S > 0 ? kSliceThreads : kGemmThreads; }
 template <int S, int KCH>
 constexpr int tail_min_waves() { return 0; }
 
-// grid (boxes, 3 mt): mt = row tiles of the box; FP64 on both paths
-__global__ void __launch_bounds__(kGemmThreads) tail_a_kernel(SweepArgs a) {
+// grid (boxes, 3 mt): mt = row tiles of the box; FP64 on both paths (held to
+// 4 waves per SIMD, which it fits in 128 registers without scratch)
+__global__ void __launch_bounds__(kGemmThreads, 4) tail_a_kernel(SweepArgs a) {
   __shared__ MfmaSmem<16> sm;
   const int mt = (a.mmax + 63) / 64;
   const XcdTile tl = xcd_tile(3 * mt);
@@ -151,8 +152,11 @@ __global__ void __launch_bounds__(kGemmThreads) tail_a_kernel(SweepArgs a) {
 // H = Q - U G2.  With nrb > 1 (levels of few boxes) every 64-row block
 // recomputes its chain's k x k product (into its own slot) so that the blocks
 // run independently.
+// (the one-chunk-per-16 variant is held to 4 waves per SIMD, which it fits
+// in 128 registers without scratch: twice the workgroups per compute unit to
+// hide its load latencies)
 template <int TK>
-__global__ void __launch_bounds__(kGemmThreads) tail_b_kernel(SweepArgs a) {
+__global__ void __launch_bounds__(kGemmThreads, (TK == 16 ? 4 : 0)) tail_b_kernel(SweepArgs a) {
   __shared__ MfmaSmem<TK> sm;
   const BoxDesc& bx = a.box[blockIdx.x];
   const int m = bx.m, k = a.k, dld = bx.dld;
