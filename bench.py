@@ -220,6 +220,27 @@ def setup_logkernel(wl, args, hbs, torch, inputs, dev):
         return (lambda: f.compress_into(Omd, Yd, Psd, Zd)), f, error
     P.build = build
 
+    def streamed(path, chunks, steps):
+        """Sampling plus compression, one after the other (chunks = 1) and with
+        the leaf level streamed behind the sampler (hbs_compress_logkernel)."""
+        f = hbs.Factors.create(tree, k, s, path, args.truncation)
+        Y2, Z2 = torch.empty_like(Omd), torch.empty_like(Psd)
+        f.compress_logkernel(xd, yd, Omd, Psd, Y2, Z2, args.sampler, 1)  # times the tiles
+        out = {"chunks": chunks, "path": path}
+        for name, c in (("sample_then_sweep_ms", 1), ("streamed_ms", chunks)):
+            f.compress_logkernel(xd, yd, Omd, Psd, Y2, Z2, args.sampler, c)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                f.compress_logkernel(xd, yd, Omd, Psd, Y2, Z2, args.sampler, c)
+            e1.record()
+            torch.cuda.synchronize()
+            f.check()
+            out[name] = e0.elapsed_time(e1) / steps
+        out["saved_ms"] = out["sample_then_sweep_ms"] - out["streamed_ms"]
+        return out
+    P.streamed = streamed
+
     def cpu():
         from oracle import logkernel as olog
         from oracle import tree as otree
@@ -413,6 +434,9 @@ def main():
     ap.add_argument("--n", type=int, default=0,
                     help="single-instance workloads: N other than the workload's own (same k, leaf, s)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--stream-chunks", type=int, default=0,
+                    help="log-kernel workloads: also time sampling plus compression with the leaf level "
+                         "streamed behind the sampler in this many row ranges")
     ap.add_argument("--cpu-subtree-level", type=int, default=4)
     ap.add_argument("--sampler", default="fp64", choices=["fp64", "bf16"])
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -472,6 +496,12 @@ def main():
     log(f"workload {args.workload}: {P.config}; sampler {P.sampler_ms:.2f} ms; truncation {args.truncation}")
     paths = ["split", "fp64"] if args.path == "both" else [args.path]
     res = {p: run_path(P, p, args, torch) for p in paths}
+    streamed = None
+    if args.stream_chunks > 1:
+        if not hasattr(P, "streamed"):
+            raise SystemExit("--stream-chunks applies to the log-kernel workloads")
+        streamed = P.streamed(paths[-1], args.stream_chunks, args.steps)
+        log(f"streamed: {streamed}")
     head = res[paths[0]]
     for p in paths:
         log(f"[{p}] tiles:\n  " + "\n  ".join(res[p]["tiles"]["steps"]))
@@ -515,6 +545,7 @@ def main():
         "rel_apply_err": head["rel_apply_err"], "power_rel_err": head["power_rel_err"],
         "paths": {p: strip(res[p]) for p in paths},
         "sampler_ms": P.sampler_ms,
+        **({"streamed": streamed} if streamed else {}),
         "sweep_tflops_nominal": model["nominal"] / (head["ms_per_step"] / 1e3) / 1e12,
         "tiles": res[paths[0]]["tiles"],
     }

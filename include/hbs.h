@@ -316,6 +316,31 @@ hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, con
                                 const double* Psi, double* Y, double* Z, int32_t s, int64_t ld,
                                 hbs_precision prec, void* hip_stream);
 
+/* Sampling and compression in one pass, streamed (section 1: the method reads
+ * the black box once, and its leaf level needs only the sample rows of its own
+ * boxes).  Writes Y and Z of the log-kernel black box above (points x, y,
+ * test matrices Omega, Psi, all as in hbs_sample_logkernel with n = the tree's
+ * N and s = the factor set's s; `sampler` is its precision, HBS_FP64 or
+ * HBS_BF16) and compresses them into f (created by hbs_factors_create for the
+ * tree of those n points), with the results of
+ *   hbs_sample_logkernel(...); hbs_compress_into(f, Omega, Y, Psi, Z, ld, ...)
+ * bit for bit.  The leaf boxes are split into `chunks` ranges of whole boxes:
+ * the sampler writes one range's rows on hip_stream while the leaf level of
+ * the range before runs on a second stream of the library's (default
+ * priority), so that the leaf level consumes each range's samples right after
+ * they are produced and overlaps the sampling of the next; the levels above
+ * the leaves follow on hip_stream.  chunks = 1, a tree of one box, the factor
+ * set's first compression (which times the tile choices step by step) and
+ * event tracing (hbs_profile) run unstreamed; chunks above the number of
+ * leaves count as that number.  Y and Z are caller-owned outputs (n x s, ld);
+ * all other pointers are borrowed as in hbs_compress_into, and the call is
+ * ordered after every earlier call on f as hbs_compress_into is.
+ * HBS_EINVAL: NULL pointers, chunks < 1, ld < s, f imported or a batch
+ * member; HBS_EUNSUPPORTED: sampler not HBS_FP64 or HBS_BF16. */
+hbs_status hbs_compress_logkernel(hbs_factors* f, const double* x, const double* y, const double* Omega,
+                                  const double* Psi, double* Y, double* Z, int64_t ld, hbs_precision sampler,
+                                  int32_t chunks, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

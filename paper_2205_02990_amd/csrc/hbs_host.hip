@@ -120,6 +120,11 @@ struct BatchImpl {
   bool tuned = false;
   hipGraphExec_t gexec = nullptr;
   hipStream_t cstream = nullptr;  // capture stream
+  // streamed sampling (hbs_compress_logkernel): the leaf level runs on this
+  // stream, each chunk after the event recorded behind its sample rows
+  hipStream_t sstream = nullptr;
+  std::vector<hipEvent_t> chunk_ev;
+  hipEvent_t join_ev = nullptr;
   // tracing
   bool prof = false;
   std::vector<Mark> marks;
@@ -159,6 +164,9 @@ struct BatchImpl {
     (void)hipDeviceSynchronize();
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (cstream) (void)hipStreamDestroy(cstream);
+    if (sstream) (void)hipStreamDestroy(sstream);
+    for (hipEvent_t e : chunk_ev) (void)hipEventDestroy(e);
+    if (join_ev) (void)hipEventDestroy(join_ev);
     for (Mark& m : marks) {
       (void)hipEventDestroy(m.a);
       (void)hipEventDestroy(m.b);
@@ -416,21 +424,29 @@ hbs_status build_sweep(BatchImpl* b) {
   return HBS_OK;
 }
 
+// The kernels of one launch step (one aligned level of one (k, s) class, or
+// a contiguous range of its boxes).
+hbs_status enqueue_launch(BatchImpl* b, const Launch& ln, hipStream_t st) {
+  HIP_TRY(b->mark_begin(ln.args.root ? 5 : 0, st));
+  HIP_TRY(hbs::launch_lq(ln.args, ln.lq, st));
+  HIP_TRY(b->mark_end(st));
+  if (ln.args.root) return HBS_OK;
+  HIP_TRY(b->mark_begin(1, st));
+  HIP_TRY(hbs::launch_col(ln.args, ln.args.svd ? 1 : 0, ln.col, st));
+  if (ln.args.svd) HIP_TRY(hbs::launch_col(ln.args, 2, ln.colj, st));
+  HIP_TRY(b->mark_end(st));
+  for (int part = 0; part < 3; ++part) {
+    HIP_TRY(b->mark_begin(2 + part, st));
+    HIP_TRY(hbs::launch_tail(ln.args, part, part == 1 ? ln.tailb : -1, st));
+    HIP_TRY(b->mark_end(st));
+  }
+  return HBS_OK;
+}
+
 hbs_status enqueue_sweep(BatchImpl* b, hipStream_t st) {
   for (const Launch& ln : b->launches) {
-    HIP_TRY(b->mark_begin(ln.args.root ? 5 : 0, st));
-    HIP_TRY(hbs::launch_lq(ln.args, ln.lq, st));
-    HIP_TRY(b->mark_end(st));
-    if (ln.args.root) continue;
-    HIP_TRY(b->mark_begin(1, st));
-    HIP_TRY(hbs::launch_col(ln.args, ln.args.svd ? 1 : 0, ln.col, st));
-    if (ln.args.svd) HIP_TRY(hbs::launch_col(ln.args, 2, ln.colj, st));
-    HIP_TRY(b->mark_end(st));
-    for (int part = 0; part < 3; ++part) {
-      HIP_TRY(b->mark_begin(2 + part, st));
-      HIP_TRY(hbs::launch_tail(ln.args, part, part == 1 ? ln.tailb : -1, st));
-      HIP_TRY(b->mark_end(st));
-    }
+    hbs_status r = enqueue_launch(b, ln, st);
+    if (r != HBS_OK) return r;
   }
   return HBS_OK;
 }
@@ -577,17 +593,25 @@ hbs_status run_sweep_body(BatchImpl* b, hipStream_t st);
 
 // Point the panel-source slots at the caller's inputs, then run the sweep:
 // replay of the captured graph, or direct launches while tracing.
+// Upload this call's panel-source table through the next pinned slot of the
+// ring (stream-ordered: the slot is reused only after its earlier upload ran).
+hipError_t stage_sources(BatchImpl* b, hipStream_t st) {
+  const int i = b->stage_next;
+  b->stage_next = (i + 1) % BatchImpl::kStage;
+  if (b->stage_used[i]) {
+    hipError_t e = hipEventSynchronize(b->stage_ev[i]);  // its earlier upload has run
+    if (e != hipSuccess) return e;
+  }
+  std::memcpy(b->h_stage[i], b->h_src.data(), sizeof(hbs::PanelSrc) * b->nsrc);
+  hipError_t e = hipMemcpyAsync(b->d_src, b->h_stage[i], sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipEventRecord(b->stage_ev[i], st);
+  if (e == hipSuccess) b->stage_used[i] = true;
+  return e;
+}
+
 hbs_status run_sweep(BatchImpl* b, hipStream_t st) {
   HIP_TRY(batch_enter(b, st));
-  {
-    const int i = b->stage_next;
-    b->stage_next = (i + 1) % BatchImpl::kStage;
-    if (b->stage_used[i]) HIP_TRY(hipEventSynchronize(b->stage_ev[i]));  // its earlier upload has run
-    std::memcpy(b->h_stage[i], b->h_src.data(), sizeof(hbs::PanelSrc) * b->nsrc);
-    HIP_TRY(hipMemcpyAsync(b->d_src, b->h_stage[i], sizeof(hbs::PanelSrc) * b->nsrc, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipEventRecord(b->stage_ev[i], st));
-    b->stage_used[i] = true;
-  }
+  HIP_TRY(stage_sources(b, st));
   hbs_status res = run_sweep_body(b, st);
   if (res != HBS_OK) return res;
   HIP_TRY(batch_leave(b, st));
@@ -1151,6 +1175,71 @@ hbs_status hbs_sample_logkernel(int64_t n, const double* x, const double* y, con
   if (n < 1 || s < 1 || ld < s || !x || !y || !Omega || !Psi || !Y || !Z) return HBS_EINVAL;
   if (prec != HBS_FP64 && prec != HBS_BF16) return HBS_EUNSUPPORTED;
   HIP_TRY(hbs::launch_logkernel(n, x, y, Omega, Psi, Y, Z, s, ld, prec, (hipStream_t)hip_stream));
+  return HBS_OK;
+}
+
+hbs_status hbs_compress_logkernel(hbs_factors* f, const double* x, const double* y, const double* Omega,
+                                  const double* Psi, double* Y, double* Z, int64_t ld, hbs_precision sampler,
+                                  int32_t chunks, void* hip_stream) {
+  if (!f || !x || !y || !Omega || !Psi || !Y || !Z || chunks < 1) return HBS_EINVAL;
+  if (sampler != HBS_FP64 && sampler != HBS_BF16) return HBS_EUNSUPPORTED;
+  BatchImpl* b = f->b.get();
+  if (!b->sweep_ready || b->inst.size() != 1) return HBS_EINVAL;  // imported sets, batch members
+  Instance& in = b->inst[0];
+  if (ld < in.s) return HBS_EINVAL;
+  const hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t n = in.tree.n;
+  const int L = in.L;
+  b->h_src[in.src_in] = hbs::PanelSrc{{Omega, Y, Psi, Z}, ld};
+  // unstreamed: one chunk, no leaf level, the first sweep (which times the
+  // tiles step by step), or event tracing
+  const int nleaf = L > 0 ? b->launches[0].args.nboxes : 0;
+  if (chunks == 1 || L == 0 || (b->autotune && !b->tuned) || b->prof) {
+    HIP_TRY(batch_enter(b, st));
+    HIP_TRY(hbs::launch_logkernel(n, x, y, Omega, Psi, Y, Z, in.s, ld, sampler, st));
+    return run_sweep(b, st);
+  }
+  chunks = std::min(chunks, nleaf);
+  if (!b->sstream) HIP_TRY(hipStreamCreateWithFlags(&b->sstream, hipStreamNonBlocking));
+  while ((int)b->chunk_ev.size() < chunks) {
+    hipEvent_t e = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    b->chunk_ev.push_back(e);
+  }
+  if (!b->join_ev) HIP_TRY(hipEventCreateWithFlags(&b->join_ev, hipEventDisableTiming));
+  HIP_TRY(batch_enter(b, st));
+  HIP_TRY(stage_sources(b, st));
+  b->last = st;
+  // The leaf step (launch 0: the leaf boxes in tree order, rows contiguous)
+  // in `chunks` ranges of whole boxes: the sampler writes a range's rows on
+  // the caller's stream, the range's boxes run on the library's stream
+  // behind it, while the sampler goes on to the next rows.
+  const Launch& leaf = b->launches[0];
+  const std::vector<int64_t>& bound = in.tree.start[L];
+  for (int c = 0; c < chunks; ++c) {
+    const int b0 = (int)((int64_t)nleaf * c / chunks), b1 = (int)((int64_t)nleaf * (c + 1) / chunks);
+    HIP_TRY(hbs::launch_logkernel(n, x, y, Omega, Psi, Y, Z, in.s, ld, sampler, st, bound[b0], bound[b1]));
+    HIP_TRY(hipEventRecord(b->chunk_ev[c], st));
+    HIP_TRY(hipStreamWaitEvent(b->sstream, b->chunk_ev[c], 0));
+    // the whole level's tile choices (the built-in heuristics depend on the
+    // box count, so they are resolved for the level, not the range)
+    Launch part = leaf;
+    if (part.lq.cfg < 0) part.lq = hbs::lq_default(leaf.args);
+    if (part.col < 0) part.col = hbs::col_default(leaf.args, leaf.args.svd ? 1 : 0);
+    if (part.args.svd && part.colj < 0) part.colj = hbs::col_default(leaf.args, 2);
+    if (part.tailb < 0) part.tailb = hbs::tail_b_default(leaf.args);
+    part.args.box = leaf.args.box + b0;
+    part.args.nboxes = b1 - b0;
+    hbs_status r = enqueue_launch(b, part, b->sstream);
+    if (r != HBS_OK) return r;
+  }
+  HIP_TRY(hipEventRecord(b->join_ev, b->sstream));
+  HIP_TRY(hipStreamWaitEvent(st, b->join_ev, 0));
+  for (size_t i = 1; i < b->launches.size(); ++i) {
+    hbs_status r = enqueue_launch(b, b->launches[i], st);
+    if (r != HBS_OK) return r;
+  }
+  HIP_TRY(batch_leave(b, st));
   return HBS_OK;
 }
 

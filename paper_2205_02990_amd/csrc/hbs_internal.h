@@ -100,11 +100,15 @@ size_t tail_workspace(int dld, int k);
 // the most box rows the split-precision products contract over
 int tail_mixed_max_rows();
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st);
+int tail_b_default(const SweepArgs& a);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_dense_small(const double* A, int64_t lda, int32_t transA, const double* Bm, int64_t ldb,
                               double* C, int64_t ldc, int32_t M, int32_t N, int32_t K, hipStream_t st);
+// rows [row0, row1) of [Y Z] = A [Omega Psi] (the sum runs over all n points;
+// row1 < 0: to n)
 hipError_t launch_logkernel(int64_t n, const double* x, const double* y, const double* Om, const double* Ps,
-                            double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, hipStream_t st);
+                            double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, hipStream_t st,
+                            int64_t row0 = 0, int64_t row1 = -1);
 
 }  // namespace hbs

@@ -43,7 +43,7 @@ __global__ void __launch_bounds__(256) logkernel_f64(int64_t n, const double* __
                                                      const double* __restrict__ y, const double* __restrict__ Om,
                                                      const double* __restrict__ Ps, double* __restrict__ Yo,
                                                      double* __restrict__ Zo, int32_t s, int64_t ld,
-                                                     int32_t nchunk) {
+                                                     int32_t nchunk, int64_t row0, int64_t row1) {
   __shared__ double Bsh[kKC][kCols];
   __shared__ double xsh[kKC], ysh[kKC];
   const int side = blockIdx.y / nchunk;
@@ -53,8 +53,8 @@ __global__ void __launch_bounds__(256) logkernel_f64(int64_t n, const double* __
   const double* __restrict__ Bsrc = side ? Ps : Om;
   double* __restrict__ Out = side ? Zo : Yo;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row = (int64_t)blockIdx.x * kRows + wave * 16 + (lane & 15);  // A-operand row of this lane
-  const bool rowok = row < n;
+  const int64_t row = row0 + (int64_t)blockIdx.x * kRows + wave * 16 + (lane & 15);  // A-operand row of this lane
+  const bool rowok = row < row1;
   const double xi = rowok ? x[row] : 0.0, yi = rowok ? y[row] : 0.0;
   d4 acc[kTiles];
 #pragma unroll
@@ -85,7 +85,7 @@ __global__ void __launch_bounds__(256) logkernel_f64(int64_t n, const double* __
       }
     }
   }
-  const int64_t rbase = (int64_t)blockIdx.x * kRows + wave * 16 + (lane >> 4);
+  const int64_t rbase = row0 + (int64_t)blockIdx.x * kRows + wave * 16 + (lane >> 4);
 #pragma unroll
   for (int t = 0; t < kTiles; ++t) {
     const int c = t * 16 + (lane & 15);
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) logkernel_f64(int64_t n, const double* __
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = rbase + 4 * r;
-        if (rr < n) Out[rr * ld + col0 + c] = acc[t][r];
+        if (rr < row1) Out[rr * ld + col0 + c] = acc[t][r];
       }
     }
   }
@@ -115,15 +115,16 @@ __device__ __forceinline__ void split_bf16(float v, __bf16& hi, __bf16& lo) {
 __global__ void __launch_bounds__(256) logkernel_bf16(int64_t n, const double* __restrict__ x,
                                                       const double* __restrict__ y, const double* __restrict__ Om,
                                                       const double* __restrict__ Ps, double* __restrict__ Yo,
-                                                      double* __restrict__ Zo, int32_t s, int64_t ld) {
+                                                      double* __restrict__ Zo, int32_t s, int64_t ld, int64_t row0,
+                                                      int64_t row1) {
   __shared__ __bf16 Bhi[kColsB][kBPad];
   __shared__ __bf16 Blo[kColsB][kBPad];
   __shared__ double xsh[kKB], ysh[kKB];
   const int c0 = blockIdx.y * kColsB;  // first column of [Omega Psi]
   const int ncol = min(kColsB, 2 * s - c0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row = (int64_t)blockIdx.x * kRows + wave * 16 + (lane & 15);  // A-operand row of this lane
-  const bool rowok = row < n;
+  const int64_t row = row0 + (int64_t)blockIdx.x * kRows + wave * 16 + (lane & 15);  // A-operand row of this lane
+  const bool rowok = row < row1;
   const double xi = rowok ? x[row] : 0.0, yi = rowok ? y[row] : 0.0;
   f32x4 acc[kTB];
 #pragma unroll
@@ -166,7 +167,7 @@ __global__ void __launch_bounds__(256) logkernel_bf16(int64_t n, const double* _
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[t], 0, 0, 0);
     }
   }
-  const int64_t rbase = (int64_t)blockIdx.x * kRows + wave * 16 + 4 * (lane >> 4);
+  const int64_t rbase = row0 + (int64_t)blockIdx.x * kRows + wave * 16 + 4 * (lane >> 4);
 #pragma unroll
   for (int t = 0; t < kTB; ++t) {
     const int cc = t * 16 + (lane & 15);
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(256) logkernel_bf16(int64_t n, const double* _
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t rr = rbase + r;
-        if (rr < n) out[rr * ld] = (double)acc[t][r];
+        if (rr < row1) out[rr * ld] = (double)acc[t][r];
       }
     }
   }
@@ -185,16 +186,21 @@ __global__ void __launch_bounds__(256) logkernel_bf16(int64_t n, const double* _
 }  // namespace
 
 hipError_t launch_logkernel(int64_t n, const double* x, const double* y, const double* Om, const double* Ps,
-                            double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, hipStream_t st) {
+                            double* Y, double* Z, int32_t s, int64_t ld, hbs_precision prec, hipStream_t st,
+                            int64_t row0, int64_t row1) {
+  if (row1 < 0) row1 = n;
+  if (row0 < 0 || row1 > n || row0 > row1) return hipErrorInvalidValue;
+  if (row0 == row1) return hipSuccess;
+  const unsigned gx = (unsigned)((row1 - row0 + kRows - 1) / kRows);
   if (prec == HBS_BF16) {
-    dim3 grid((unsigned)((n + kRows - 1) / kRows), (2 * s + kColsB - 1) / kColsB);
-    hipLaunchKernelGGL(logkernel_bf16, grid, dim3(256), 0, st, n, x, y, Om, Ps, Y, Z, s, ld);
+    dim3 grid(gx, (2 * s + kColsB - 1) / kColsB);
+    hipLaunchKernelGGL(logkernel_bf16, grid, dim3(256), 0, st, n, x, y, Om, Ps, Y, Z, s, ld, row0, row1);
     return hipGetLastError();
   }
   if (prec != HBS_FP64) return hipErrorInvalidValue;
   const int nchunk = (s + kCols - 1) / kCols;
-  dim3 grid((unsigned)((n + kRows - 1) / kRows), 2 * nchunk);
-  hipLaunchKernelGGL(logkernel_f64, grid, dim3(256), 0, st, n, x, y, Om, Ps, Y, Z, s, ld, nchunk);
+  dim3 grid(gx, 2 * nchunk);
+  hipLaunchKernelGGL(logkernel_f64, grid, dim3(256), 0, st, n, x, y, Om, Ps, Y, Z, s, ld, nchunk, row0, row1);
   return hipGetLastError();
 }
 

@@ -227,6 +227,9 @@ size_t tail_workspace(int dld, int k) {
 
 int tail_mixed_max_rows() { return kSliceChunks * kSliceK; }
 
+// few boxes: latency bound, row blocks in parallel and deeper K chunks
+int tail_b_default(const SweepArgs& a) { return a.nboxes < 256 ? 1 : 0; }
+
 namespace {
 
 // the split-precision launch of tail_a or tail_c for S slices, with one
@@ -260,8 +263,7 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
   if (part == 0) {
     hipLaunchKernelGGL(tail_a_kernel, xcd_grid(a.nboxes, 3 * mt), dim3(kGemmThreads), 0, st, a);
   } else if (part == 1) {
-    // few boxes: latency bound, row blocks in parallel and deeper K chunks
-    if (variant < 0) variant = a.nboxes < 256 ? 1 : 0;
+    if (variant < 0) variant = tail_b_default(a);
     if (variant == 1)
       hipLaunchKernelGGL(tail_b_kernel<32>, dim3(a.nboxes, 2 * mt), dim3(kGemmThreads), 0, st, a);
     else

@@ -69,6 +69,7 @@ def load():
         "hbs_check": (I32, [P]),
         "hbs_status_str": (ctypes.c_char_p, [I32]),
         "hbs_sample_logkernel": (I32, [I64, VP, VP, VP, VP, VP, VP, I32, I64, I32, VP]),
+        "hbs_compress_logkernel": (I32, [P, VP, VP, VP, VP, VP, VP, I64, I32, I32, VP]),
         "hbs_profile": (I32, [P, ctypes.c_int]),
         "hbs_profile_read": (I32, [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64), I32]),
         "hbs_batch_create": (I32, [I32, ctypes.POINTER(P), ctypes.POINTER(I32), ctypes.POINTER(I32), I32,
@@ -184,6 +185,21 @@ class Factors:
                 raise ValueError("Omega, Y, Psi, Z must share one leading dimension")
         _check(load().hbs_compress_into(self._h, _dev_f64(Om, "Omega"), _dev_f64(Y, "Y"), _dev_f64(Ps, "Psi"),
                                         _dev_f64(Z, "Z"), ld, _stream(stream)), "hbs_compress_into")
+        return self
+
+    def compress_logkernel(self, x: torch.Tensor, y: torch.Tensor, Om: torch.Tensor, Ps: torch.Tensor,
+                           Y: torch.Tensor, Z: torch.Tensor, sampler: str = "fp64", chunks: int = 8, stream=None):
+        """Sample the log kernel on points (x, y) into Y, Z and compress them,
+        the leaf level streamed behind the sampler in `chunks` row ranges
+        (hbs_compress_logkernel)."""
+        ld = Om.stride(0)
+        for t in (Y, Ps, Z):
+            if t.stride(0) != ld:
+                raise ValueError("Omega, Y, Psi, Z must share one leading dimension")
+        _check(load().hbs_compress_logkernel(self._h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                             _dev_f64(Om, "Omega"), _dev_f64(Ps, "Psi"), _dev_f64(Y, "Y"),
+                                             _dev_f64(Z, "Z"), ld, PRECISION[sampler], int(chunks), _stream(stream)),
+               "hbs_compress_logkernel")
         return self
 
     def apply(self, X: torch.Tensor, transpose: bool = False, out: torch.Tensor | None = None, stream=None):

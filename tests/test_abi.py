@@ -131,3 +131,13 @@ def test_reporting_entry_points_validate_before_device_work():
     pts = hbs.LogKernelPoints(0, 8, 8)
     assert lib.hbs_matvec_logkernel(ctypes.cast(ctypes.pointer(pts), ctypes.c_void_p), 0, dummy, dummy,
                                     None) == hbs.HBS_EINVAL
+
+
+def test_streamed_sampling_rejects_null_arguments():
+    """hbs_compress_logkernel checks its arguments before any device work:
+    a NULL factor set or NULL arrays are HBS_EINVAL (no GPU needed)."""
+    hbs = _lib()
+    lib = hbs.load()
+    one = ctypes.c_void_p(8)
+    assert lib.hbs_compress_logkernel(None, one, one, one, one, one, one, 160, 0, 8, None) == hbs.HBS_EINVAL
+    assert lib.hbs_compress_logkernel(None, None, one, one, one, one, one, 160, 0, 8, None) == hbs.HBS_EINVAL
