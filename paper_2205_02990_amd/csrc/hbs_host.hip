@@ -573,7 +573,7 @@ hipError_t tune_sweep(BatchImpl* b, hipStream_t st) {
       ln.tailb = v.first;
     } else if (e == hipSuccess) {
       float best = 1e30f;
-      for (int var = 0; var < 2 && e == hipSuccess; ++var) {
+      for (int var = 0; var < hbs::tail_b_variants(a) && e == hipSuccess; ++var) {
         float t = 0.0f;
         e = time_twice([&] { return hbs::launch_tail(a, 1, var, st); }, e0, e1, st, &t);
         if (e == hipSuccess && t < best) best = t, ln.tailb = var;

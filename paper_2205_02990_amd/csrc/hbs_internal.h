@@ -95,12 +95,16 @@ int64_t factors_n(const hbs_factors* f);
 hipError_t launch_col(const SweepArgs& a, int mode, int cfg, hipStream_t st);
 // the products after the bases: part 0 (tail_a), 1 (tail_b), 2 (tail_c);
 // variant (tail_b only): 0 one workgroup per chain, 1 row blocks in
-// parallel with deeper K chunks, < 0 the heuristic (1 on levels of few boxes)
+// parallel with deeper K chunks, 2 small boxes staged whole, < 0 the
+// heuristic (1 on levels of few boxes)
 size_t tail_workspace(int dld, int k);
 // the most box rows the split-precision products contract over
 int tail_mixed_max_rows();
 hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st);
 int tail_b_default(const SweepArgs& a);
+// tail_b variants valid for a launch: 0 and 1 always, 2 (both operands staged
+// at once) for boxes of at most 64 rows with k <= 32
+int tail_b_variants(const SweepArgs& a);
 hipError_t launch_apply_up(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_apply_down(const ApplyArgs& a, hipStream_t st);
 hipError_t launch_dense_small(const double* A, int64_t lda, int32_t transA, const double* Bm, int64_t ldb,

@@ -66,6 +66,8 @@ struct TailWs {
 // which keeps grid x times workgroup size within the 32-bit launch limit at
 // any box count.  (tail_b's two chains share no operand and keep the plain
 // two-dimensional grid, which measured faster.)
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kXcds = 8;
 constexpr int64_t kXcdGridX = (int64_t)1 << 21;
 
@@ -179,6 +181,101 @@ __global__ void __launch_bounds__(kGemmThreads, (TK == 16 ? 4 : 0)) tail_b_kerne
     }
 }
 
+// tail_b for boxes of at most 64 rows and k <= 32 (variant 2), grid (boxes,
+// 2 chains): both m x k operands of the chain are staged in LDS at once (all
+// loads in flight together, one wait instead of one per 16-deep chunk), then
+// G = B1^* B2 and Out = B2 - B1 G on the matrix cores from LDS, and for
+// chain 0 T = T0 - E^* through LDS.  Rows past m and columns past k are zero.
+constexpr int kSmallM = 64, kSmallK = 32;
+struct SmallBSmem {
+  double b1[kSmallM][kSmallK + 1];  // B1 = V or U (m x k); later E or H
+  double b2[kSmallM][kSmallK + 1];  // B2 = F or Q (m x k)
+  double g[kSmallK][kSmallK + 1];   // G = B1^* B2 (k x k)
+};
+__global__ void __launch_bounds__(kGemmThreads) tail_b_small_kernel(SweepArgs a) {
+  __shared__ SmallBSmem sm;
+  const BoxDesc& bx = a.box[blockIdx.x];
+  const int m = bx.m, k = a.k, dld = bx.dld;
+  const int chain = blockIdx.y;
+  TailWs ws(bx.T, dld, k);
+  const double* B1 = chain ? bx.U : bx.V;
+  const double* B2 = chain ? ws.Q : ws.F;
+  double* Out = chain ? ws.H : ws.E;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  // ---- stage B1, B2 (row-major m x k, row stride k) ------------------------
+  constexpr int PER = kSmallM * kSmallK / kGemmThreads;  // 8 per thread and operand
+  double v1[PER], v2[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + kGemmThreads * q, i = idx / kSmallK, j = idx % kSmallK;
+    const bool ok = i < m && j < k;
+    const double x1 = B1[ok ? i * k + j : 0], x2 = B2[ok ? i * k + j : 0];
+    v1[q] = ok ? x1 : 0.0;
+    v2[q] = ok ? x2 : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int idx = tid + kGemmThreads * q, i = idx / kSmallK, j = idx % kSmallK;
+    sm.b1[i][j] = v1[q];
+    sm.b2[i][j] = v2[q];
+  }
+  __syncthreads();
+  // ---- G = B1^* B2: 16 x 16 tiles of G, one per wave, K = 64 rows ---------
+  // (v_mfma_f64_16x16x4f64: lane l supplies A(l % 16, l / 16), B(l / 16,
+  // l % 16) and receives C(l / 16 + 4 e, l % 16) in element e)
+  const int kt = (k + 15) / 16;
+  if (wv < kt * kt) {
+    const int i0 = 16 * (wv / kt), j0 = 16 * (wv % kt);
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < kSmallM; kk += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.b1[kk + lk][i0 + li], sm.b2[kk + lk][j0 + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) sm.g[i0 + lk + 4 * e][j0 + li] = acc[e];
+  }
+  __syncthreads();
+  // ---- Out = B2 - B1 G: (m/16) x (k/16) tiles dealt to the waves, K = k ----
+  const int mtl = (m + 15) / 16, nt = mtl * kt;
+  f64x4 oacc[2];  // at most 4 x 2 tiles over 4 waves
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    oacc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const int tile = wv + 4 * t;
+    if (tile < nt) {
+      const int i0 = 16 * (tile / kt), j0 = 16 * (tile % kt);
+#pragma unroll
+      for (int kk = 0; kk < kSmallK; kk += 4)
+        if (kk < 16 * kt)
+          oacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.b1[i0 + li][kk + lk], sm.g[kk + lk][j0 + li], oacc[t],
+                                                         0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave has read B1 before it is overwritten with Out
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int tile = wv + 4 * t;
+    if (tile < nt) {
+      const int i0 = 16 * (tile / kt), j0 = 16 * (tile % kt);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + lk + 4 * e, j = j0 + li;
+        const double o = sm.b2[i][j] - oacc[t][e];
+        sm.b1[i][j] = o;
+        if (i < m && j < k) Out[i * k + j] = o;
+      }
+    }
+  }
+  if (chain == 0) {
+    __syncthreads();
+    // T = T0 - E^* (k x m, row stride dld)
+    for (int idx = tid; idx < k * m; idx += kGemmThreads) {
+      const int i = idx / m, j = idx % m;
+      ws.T[i * dld + j] = ws.T0[i * dld + j] - sm.b1[j][i];
+    }
+  }
+}
+
 // grid (boxes, mt^2 + 2 st)
 template <int S, int KCH = kSliceChunks>
 __global__ void __launch_bounds__(tail_threads<S>(), (tail_min_waves<S, KCH>())) tail_c_kernel(SweepArgs a) {
@@ -229,6 +326,7 @@ int tail_mixed_max_rows() { return kSliceChunks * kSliceK; }
 
 // few boxes: latency bound, row blocks in parallel and deeper K chunks
 int tail_b_default(const SweepArgs& a) { return a.nboxes < 256 ? 1 : 0; }
+int tail_b_variants(const SweepArgs& a) { return (a.k <= kSmallK && a.mmax <= kSmallM) ? 3 : 2; }
 
 namespace {
 
@@ -264,7 +362,10 @@ hipError_t launch_tail(const SweepArgs& a, int part, int variant, hipStream_t st
     hipLaunchKernelGGL(tail_a_kernel, xcd_grid(a.nboxes, 3 * mt), dim3(kGemmThreads), 0, st, a);
   } else if (part == 1) {
     if (variant < 0) variant = tail_b_default(a);
-    if (variant == 1)
+    if (variant == 2) {
+      if (a.k > kSmallK || a.mmax > kSmallM) return hipErrorInvalidValue;
+      hipLaunchKernelGGL(tail_b_small_kernel, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
+    } else if (variant == 1)
       hipLaunchKernelGGL(tail_b_kernel<32>, dim3(a.nboxes, 2 * mt), dim3(kGemmThreads), 0, st, a);
     else
       hipLaunchKernelGGL(tail_b_kernel<16>, dim3(a.nboxes, 2), dim3(kGemmThreads), 0, st, a);
