@@ -656,7 +656,7 @@ def trace_summary(db_path, workload, sweeps=3):
                f"average {sum(steady) / len(steady) / 1e3:.1f} us, {sum(steady) / sweeps / 1e6:.3f} ms per sweep.")
     # every sweep kernel of the last `sweeps` sweeps, by step of the sweep
     # (a step starts at its QR-kernel launch)
-    kinds = ("lq_kernel", "col_kernel", "tail_a_kernel", "tail_b_kernel", "tail_c_kernel")
+    kinds = ("lq_kernel", "col_kernel", "tail_a", "tail_b", "tail_c")  # tail_b has two kernels
     sw = [r for r in rows if any(k in r[0] for k in kinds)]
     first = next(i for i in range(len(sw)) if sw[i] is lq[0])
     per_step = collections.defaultdict(lambda: collections.defaultdict(list))
@@ -675,7 +675,7 @@ def trace_summary(db_path, workload, sweeps=3):
         if targs and targs.group(1).replace(" ", "").split(",")[-1] == "2":
             kind = "col_kernel (Jacobi)"
         per_step[st][kind].append(dur)
-    cols = ["lq_kernel", "col_kernel", "col_kernel (Jacobi)", "tail_a_kernel", "tail_b_kernel", "tail_c_kernel"]
+    cols = ["lq_kernel", "col_kernel", "col_kernel (Jacobi)", "tail_a", "tail_b", "tail_c"]
     cols = [c for c in cols if any(c in d for d in per_step.values())]
     out.append("")
     out.append(f"Per step of the sweep (average over the last {sweeps} sweeps, us; a step is one aligned level "

@@ -101,7 +101,7 @@ def test_trace_summary_per_step(tmp_path):
                 break
             launch(col1, scale * 2000)
             launch(col2, scale * 300)
-            for t in ("tail_a_kernel<0, 2>", "tail_b_kernel<16>", "tail_c_kernel<0, 2>"):
+            for t in ("tail_a_kernel", "tail_b_small_kernel", "tail_c_kernel<0, 2>"):
                 launch(f"void hbs::(anonymous namespace)::{t}(hbs::SweepArgs)", scale * 500)
     launch("apply_up_kernel", 10 ** 9)  # after the sweeps: not part of any step
     con.executemany("insert into kernels values (?, ?, ?, ?, ?, ?, ?)", rows)
