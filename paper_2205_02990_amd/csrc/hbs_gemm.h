@@ -6,7 +6,10 @@
 //              L^T and per column of R), the slice pairs multiplied exactly on
 //              v_mfma_i32_16x16x64_i8 with 32-bit integer sums, recombined in
 //              FP64 (error-free slicing in the manner of Ozaki, Ogita, Oishi
-//              and Rump, with integer slices).
+//              and Rump, with integer slices);
+//   parent_mfma / parent_sliced  the two parent blocks of one side of a box
+//              as one product over two blocks of contracted indices (FP64,
+//              or sliced with scales of their own per block).
 #pragma once
 
 #include <hip/hip_runtime.h>
