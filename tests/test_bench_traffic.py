@@ -120,3 +120,38 @@ def test_trace_summary_per_step(tmp_path):
             assert [float(x) for x in r[4:9]] == pytest.approx([2.0, 0.3, 0.5, 0.5, 0.5])
         else:
             assert r[4:9] == [""] * 5
+
+
+def test_counter_summary_means_per_dispatch(tmp_path):
+    """bench.py --counter-summary: per kernel name (template arguments kept,
+    namespaces dropped), the number of dispatches and the mean of each counter
+    per dispatch."""
+    path = tmp_path / "counters.csv"
+    rows = []
+    for d, (kern, vals) in enumerate([
+            ("void hbs::(anonymous namespace)::tail_c_kernel<8, 1>(hbs::SweepArgs)", {"SQ_INSTS_VALU": 10.0, "SQ_BUSY_CU_CYCLES": 4.0}),
+            ("void hbs::(anonymous namespace)::tail_c_kernel<8, 1>(hbs::SweepArgs)", {"SQ_INSTS_VALU": 30.0, "SQ_BUSY_CU_CYCLES": 8.0}),
+            ("hbs::(anonymous namespace)::tail_a_kernel(hbs::SweepArgs)", {"SQ_INSTS_VALU": 5.0})]):
+        for name, v in vals.items():
+            rows.append(dict(Correlation_Id=d, Dispatch_Id=d, Kernel_Name=kern, Counter_Name=name, Counter_Value=v))
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=FIELDS)
+        w.writeheader()
+        w.writerows(rows)
+    md = bench.counter_summary(str(path)).splitlines()
+    assert md[0] == "| kernel | dispatches | SQ_BUSY_CU_CYCLES | SQ_INSTS_VALU |"
+    body = {ln.split("|")[1].strip(): [c.strip() for c in ln.split("|")[2:-1]] for ln in md[2:]}
+    assert body["void tail_c_kernel<8, 1>"] == ["2", "6", "20"]
+    assert body["tail_a_kernel"] == ["1", "", "5"]
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
